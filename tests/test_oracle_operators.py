@@ -1,0 +1,192 @@
+"""Pins of the oracle's operators: masked grad / div (Sec. IV-B boundary
+conditions), projections and resolvent (Eqs. (11), (13)), tensor (Eq. (12)),
+preconditioned step sizes (Sec. III-D).
+
+Checks are against definitions written out independently here (sparse
+matrices built entry by entry, brute-force minimisation, eigen-decomposition).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+
+
+def _random_mask(rng, H, W, p=0.85):
+    return (rng.random((H, W)) < p).astype(np.uint8)
+
+
+def _grad_matrix(mask):
+    """Sparse forward-difference gradient with the mask condition, written
+    from its definition: component x of pixel P is u(P+x) - u(P) if P and P+x
+    are both inside the image and the mask, else 0 (likewise y)."""
+    H, W = mask.shape
+    rows, cols, vals = [], [], []
+    for i in range(H):
+        for j in range(W):
+            P = i * W + j
+            if mask[i, j] and j + 1 < W and mask[i, j + 1]:
+                rows += [2 * P, 2 * P]
+                cols += [P + 1, P]
+                vals += [1.0, -1.0]
+            if mask[i, j] and i + 1 < H and mask[i + 1, j]:
+                rows += [2 * P + 1, 2 * P + 1]
+                cols += [P + W, P]
+                vals += [1.0, -1.0]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(2 * H * W, H * W))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_grad_div_adjoint(seed):
+    rng = np.random.default_rng(seed)
+    H, W = 23, 31
+    m = _random_mask(rng, H, W)
+    u = rng.normal(size=(H, W))
+    p = rng.normal(size=(H, W, 2))
+    g = oracle.grad(u, m)
+    d = oracle.div(p, m)
+    lhs = np.sum(g * p)
+    rhs = -np.sum(u * d)
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + 1)
+    # and grad is exactly the matrix of the definition
+    G = _grad_matrix(m)
+    assert np.array_equal(g.reshape(-1), G @ u.reshape(-1))
+
+
+def test_projections():
+    rng = np.random.default_rng(7)
+    for n in (2, 4):
+        phi = rng.normal(size=(5000, n)) * rng.uniform(0.01, 3.0, (5000, 1))
+        P = oracle.project_balls(phi, n).reshape(-1, n)
+        nrm = np.linalg.norm(phi, axis=1)
+        assert np.all(np.linalg.norm(P, axis=1) <= 1 + 1e-15)
+        inside = nrm <= 1
+        assert np.array_equal(P[inside], phi[inside])
+        assert np.allclose(P[~inside], phi[~inside] / nrm[~inside, None], rtol=0, atol=1e-15)
+        assert np.max(np.abs(oracle.project_balls(P, n).reshape(-1, n) - P)) <= 4e-16
+
+
+def test_threshold_is_the_prox_of_the_linearised_l1_term():
+    """Eq. (13) (third case read with the sign that zeroes rho_bar) equals the
+    argmin of (u - uhat)^2 / (2 tau) + lambda |rho_c + u I_u|, found by a
+    dense 1-D search refined by golden-section search."""
+    rng = np.random.default_rng(8)
+    n = 20000
+    uhat = rng.normal(0, 2, n)
+    rho = rng.normal(0, 0.2, n)
+    Iu = rng.normal(0, 0.1, n)
+    Iu[:500] = 0.0                                   # no data
+    tau = rng.uniform(0.01, 1.0, n)
+    lam = 50.0
+    # cases on the tie boundaries |rho_bar| = tau lam Iu^2
+    k = slice(500, 1000)
+    s = np.where(rng.random(500) < 0.5, -1.0, 1.0)
+    rho[k] = s * tau[k] * lam * Iu[k] ** 2 - uhat[k] * Iu[k]
+    out = oracle.threshold(uhat, rho, Iu, tau, lam)
+
+    def f(u):
+        return (u - uhat[:, None]) ** 2 / (2 * tau[:, None]) + lam * np.abs(rho[:, None] + u * Iu[:, None])
+
+    span = 2 * tau * lam * np.abs(Iu) + 1e-3
+    grid = uhat[:, None] + span[:, None] * np.linspace(-1.5, 1.5, 3001)[None, :]
+    best = grid[np.arange(n), np.argmin(f(grid), axis=1)]
+    a = best - 3 * span / 3000
+    b = best + 3 * span / 3000
+    g = (np.sqrt(5) - 1) / 2
+    for _ in range(120):
+        c = b - g * (b - a)
+        d = a + g * (b - a)
+        left = f(c[:, None])[:, 0] < f(d[:, None])[:, 0]
+        b = np.where(left, d, b)
+        a = np.where(left, a, c)
+    brute = 0.5 * (a + b)
+    fo = f(out[:, None])[:, 0]
+    fb = f(brute[:, None])[:, 0]
+    assert np.all(fo <= fb + 1e-10 * (1 + np.abs(fb)))
+    assert np.max(np.abs(out - brute) / (1 + np.abs(brute))) < 1e-6
+    assert np.array_equal(out[:500], uhat[:500])
+
+
+def test_tensor_eigen_structure():
+    rng = np.random.default_rng(9)
+    H, W = 40, 48
+    jj, ii = np.meshgrid(np.arange(W), np.arange(H))
+    J = 0.5 + 0.2 * np.sin(0.3 * jj + 0.1 * ii) + 0.1 * np.cos(0.17 * ii - 0.05 * jj * jj / W)
+    m = np.ones((H, W), np.uint8)
+    beta, eta = 9.0, 0.85
+    T = oracle.tensor(J, m, beta, eta)
+    # interior gradient by central differences, written out here
+    gx = 0.5 * (J[1:-1, 2:] - J[1:-1, :-2])
+    gy = 0.5 * (J[2:, 1:-1] - J[:-2, 1:-1])
+    Ti = T[1:-1, 1:-1]
+    for t, x, y in zip(Ti.reshape(-1, 3), gx.reshape(-1), gy.reshape(-1)):
+        M = np.array([[t[0], t[1]], [t[1], t[2]]])
+        g = np.hypot(x, y)
+        e = np.exp(-beta * g ** eta)
+        n = np.array([x, y]) / g
+        assert np.allclose(M @ n, e * n, atol=1e-14)
+        nperp = np.array([-n[1], n[0]])
+        assert np.allclose(M @ nperp, nperp, atol=1e-14)
+    # constant image and masked-out pixels: identity
+    Tc = oracle.tensor(np.full((H, W), 0.3), m, beta, eta)
+    assert np.array_equal(Tc, np.broadcast_to([1.0, 0.0, 1.0], Tc.shape))
+    m2 = _random_mask(rng, H, W, 0.5)
+    T2 = oracle.tensor(J, m2, beta, eta)
+    assert np.array_equal(T2[m2 == 0], np.broadcast_to([1.0, 0.0, 1.0], T2[m2 == 0].shape))
+
+
+def test_tensor_one_sided_at_mask_border():
+    J = np.arange(5 * 6, dtype=np.float64).reshape(5, 6) ** 1.5 / 10
+    m = np.ones((5, 6), np.uint8)
+    m[:, 4:] = 0
+    T = oracle.tensor(J, m, 2.0, 1.0)
+    i, j = 2, 3            # right neighbour is masked: backward difference in x
+    gx = J[i, j] - J[i, j - 1]
+    gy = 0.5 * (J[i + 1, j] - J[i - 1, j])
+    g = np.hypot(gx, gy)
+    M = np.array([[T[i, j, 0], T[i, j, 1]], [T[i, j, 1], T[i, j, 2]]])
+    n = np.array([gx, gy]) / g
+    assert np.allclose(M @ n, np.exp(-2.0 * g) * n, atol=1e-14)
+
+
+@pytest.mark.parametrize("reg", ["tgv", "tv"])
+def test_steps_are_reciprocal_abs_sums_of_K(reg):
+    """Diagonal preconditioning with alpha = 1: sigma = 1 / (row abs-sum),
+    tau = 1 / (column abs-sum) of K = [[a1 T grad, -a1 I], [0, a0 grad]]
+    assembled explicitly (TV: K = [a1 T grad])."""
+    rng = np.random.default_rng(10)
+    H, W = 12, 12
+    m = _random_mask(rng, H, W, 0.8)
+    J = rng.random((H, W))
+    T = oracle.tensor(J, m, 9.0, 0.85)
+    a0, a1 = 17.0, 1.2
+    n = H * W
+    G = _grad_matrix(m).tocsr()
+    Gx, Gy = G[0::2], G[1::2]
+    t11 = sp.diags(T[..., 0].reshape(-1))
+    t12 = sp.diags(T[..., 1].reshape(-1))
+    t22 = sp.diags(T[..., 2].reshape(-1))
+    TG = sp.vstack([t11 @ Gx + t12 @ Gy, t12 @ Gx + t22 @ Gy])          # rows p1, p2
+    if reg == "tgv":
+        I = sp.identity(n)
+        K = sp.bmat([[a1 * TG[:n], -a1 * I, None],
+                     [a1 * TG[n:], None, -a1 * I],
+                     [None, a0 * Gx, None], [None, a0 * Gy, None],
+                     [None, None, a0 * Gx], [None, None, a0 * Gy]]).tocsr()
+    else:
+        K = (a1 * TG).tocsr()
+    A = abs(K)
+    row = np.asarray(A.sum(axis=1)).reshape(-1)
+    col = np.asarray(A.sum(axis=0)).reshape(-1)
+    sp_, tu, tv = oracle.steps(T, m, a0, a1, reg)
+    rp = np.maximum(row[:n], row[n:2 * n])
+    ok = rp > 0
+    assert np.allclose(sp_.reshape(-1)[ok], 1.0 / rp[ok], rtol=1e-14, atol=0)
+    cu = col[:n]
+    ok = cu > 0
+    assert np.allclose(tu.reshape(-1)[ok], 1.0 / cu[ok], rtol=1e-14, atol=0)
+    if reg == "tgv":
+        assert np.allclose(tv.reshape(-1), 1.0 / col[n:2 * n], rtol=1e-14, atol=0)
+        assert np.allclose(tv.reshape(-1), 1.0 / col[2 * n:], rtol=1e-14, atol=0)
+        # every q row has abs-sum 2 a0 or 0: sigma_q = 1/(2 a0) is the smallest safe value
+        assert np.max(row[2 * n:]) == 2 * a0
