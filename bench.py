@@ -1,0 +1,161 @@
+"""Benchmark: primal-dual Mpixel-iterations per second of the whole method on
+one MI355X, with the level-0 primal-dual kernel against the HBM roofline and
+the FP64 CPU oracle timed beside it.
+
+A step is one whole batched solve (pre-rotation, pyramids, every level x
+warp x primal-dual iteration, triangulation) of the workload's pairs, inputs
+already resident in HBM.  Default workload: 8 pairs of 2048x2048
+Kannala-Brandt 200-degree fisheye images (seeded box-and-sphere rooms),
+7 levels x 15 warps x 200 iterations, FP32 TGV-L1.
+
+Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+[--config c5|c3|c2|c1] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic HBM bytes of one level-0 primal-dual pixel-iteration of the
+# fused FP32 TGV kernel: reads u 4, v 8, p 8, q 16, tensor pack 16, rho_c 4,
+# flags 1 (57 B); writes u 4, v 8, p 8, q 16 (36 B).
+BYTES_PER_PIX_ITER = 93
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c5")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the path shards "
+              "by image pair across GPUs but no multi-GPU run is part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1909_07545_amd as vfs
+    from synth import configs, scene
+
+    cfg = configs.get(args.config)
+    params = configs.solver_params(cfg)
+    rig = scene.make_rig(cfg)
+    n = cfg["batch"]
+    log(f"bench: rendering {n} pair(s) of {cfg['width']}x{cfg['height']} ({cfg['name']})")
+    t0 = time.time()
+    pairs = [scene.render_pair(rig, cfg, b, with_gt=False)[:2] for b in range(n)]
+    tens = [scene.pair_tensor_params(cfg, b) for b in range(n)]
+    log(f"bench: inputs ready in {time.time() - t0:.1f} s")
+
+    dev = torch.device("cuda:0")
+    I0s = [torch.from_numpy(p[0]).to(dev) for p in pairs]
+    I1s = [torch.from_numpy(p[1]).to(dev) for p in pairs]
+    R = vfs.Rig(rig["cam0"], rig["cam1"], rig["R"], rig["t"], params["levels"])
+    betas = [b for b, _ in tens]
+    etas = [e for _, e in tens]
+    outs = None
+    for i in range(args.warmup):
+        outs = vfs.solve_batch(R, I0s, I1s, params, betas=betas, etas=etas, out=outs)
+        torch.cuda.synchronize()
+        log(f"bench: warmup step {i} done")
+    vfs.profile_enable(R, True)
+    vfs.profile_read(R, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        outs = vfs.solve_batch(R, I0s, I1s, params, betas=betas, etas=etas, out=outs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pd_ms, pd_launches = vfs.profile_read(R, reset=True)
+    vfs.profile_enable(R, False)
+    log(f"bench: {args.steps} timed steps in {dt:.3f} s")
+
+    pix_iter = configs.pix_iters(cfg)
+    ms_per_step = 1e3 * dt / args.steps
+    value = pix_iter / (dt / args.steps) / 1e6
+
+    W, H = cfg["width"], cfg["height"]
+    avg_launch_s = (pd_ms / pd_launches) / 1e3 if pd_launches else float("nan")
+    bytes_per_launch = BYTES_PER_PIX_ITER * W * H * n
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "pd_kernel<PD_FUSED, TGV> at level 0",
+                "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": pd_launches,
+                "bytes_per_launch": bytes_per_launch}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, rig, pairs[0], tens[0], params, args.cpu_seconds)
+
+    line = {
+        "metric": "primal-dual Mpix-iter/s", "value": round(value, 1), "unit": "Mpix-iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded rendered fisheye rooms)",
+        "config": {"workload": f"{args.config} {cfg['name']}: {n} x {W}x{H} {cfg['model']} {cfg['fov_deg']:.0f}deg, "
+                               f"{cfg['levels']} levels x {cfg['warps']} warps x {cfg['iters']} iters, FP32 TGV-L1",
+                   "pairs": n, "width": W, "height": H, "levels": cfg["levels"], "warps": cfg["warps"],
+                   "iters": cfg["iters"], "pix_iter_per_step": pix_iter},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(cfg, rig, pair, tens, params, seconds):
+    """The FP64 oracle's primal-dual iterations (the hot loop) on pair 0's
+    full-resolution level-0 problem, for a bounded number of iterations."""
+    import numpy as np
+
+    import oracle
+
+    I0 = pair[0].astype(np.float64)
+    I1 = pair[1].astype(np.float64)
+    cam0, R, t = rig["cam0"], rig["R"], rig["t"]
+    log("bench: cpu baseline set-up (oracle, level 0 of pair 0)")
+    cf, _ = oracle.calibration_field(cam0, rig["cam1"], R)
+    J1 = oracle.prerotate(I1, cf)
+    m = oracle.mask0(cam0)
+    dv = oracle.data_valid(cam0, rig["cam1"], R, t, 0)
+    gam, _ = oracle.trajectory_field(cam0, R, t, 0)
+    beta, eta = tens
+    T = oracle.tensor(I0, m, beta, eta)
+    sp, tu, tv = oracle.steps(T, m, params["alpha0"], params["alpha1"])
+    H, W = m.shape
+    u = np.zeros((H, W))
+    w = np.zeros((H, W, 2))
+    _, _, Iu, rho = oracle.linearise(I0, J1, gam, dv, u, w)
+    z2, z4 = np.zeros((H, W, 2)), np.zeros((H, W, 4))
+    t0 = time.perf_counter()
+    st = oracle.pd_iterations(params, T, m, sp, tu, tv, Iu, rho, u, z2, z2, z4, 2)
+    per_iter = (time.perf_counter() - t0) / 2
+    k = int(max(2, min(200, seconds / max(per_iter, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.pd_iterations(params, T, m, sp, tu, tv, Iu, rho, st["u"], st["v"], st["p"], st["q"], k,
+                         ubar=st["ubar"], vbar=st["vbar"])
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    val = W * H * k / dt / 1e6
+    log(f"bench: cpu baseline {k} iterations in {dt:.1f} s")
+    return {"value": round(val, 2), "unit": "Mpix-iter/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} primal-dual iterations of Eq. (11) on pair 0's full {W}x{H} level-0 problem "
+                      f"(FP64 C oracle, OpenMP over rows), {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

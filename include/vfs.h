@@ -1,0 +1,205 @@
+/*
+ * vfs.h -- C ABI of the MI355X (gfx950) implementation of non-rectified
+ * variational fisheye stereo (Roxas & Oishi, "Real-Time Variational Fisheye
+ * Stereo without Rectification and Undistortion", arXiv 1909.07545).
+ *
+ * The calls follow the paper's statement of the problem: a calibration
+ * (fisheye intrinsics of both cameras and the pose X1 = R X0 + t) becomes a
+ * rig holding the trajectory fields (Sec. III-B) and the calibration field
+ * (Sec. IV-A); an image pair becomes the scalar displacement u along the
+ * epipolar curves, the warping vectors w (Sec. III-C, Eqs. (8)-(9)) and the
+ * triangulated depth (Sec. III-D, last paragraph), by Algorithm 1 run inside
+ * the coarse-to-fine scheme of Sec. IV-B.
+ *
+ * Conventions shared by every call:
+ *  - Images are row-major float32, intensities in [0, 1]; pixel (i = row,
+ *    j = column) sits at integer coordinates (j, i) (pixel centres).
+ *  - Every pointer argument marked "device" is memory of the current HIP
+ *    device (for example a torch CUDA tensor's data_ptr()); "host" pointers
+ *    are ordinary process memory.  Pitches are in bytes.
+ *  - Work is enqueued asynchronously on the hip_stream argument (a
+ *    hipStream_t; NULL means the default stream).  No call synchronises the
+ *    stream except where stated.  Device faults surface at the caller's next
+ *    synchronisation.
+ *  - Every call returns a vfs_status; arguments are validated before any
+ *    device work is enqueued, and nothing is enqueued on error.  The message
+ *    of the last error of the calling thread is vfs_last_error().
+ *  - The library owns rig handles and their device memory (freed by
+ *    vfs_rig_destroy); the caller owns every image and output buffer and must
+ *    keep them alive until the enqueued work completes.
+ */
+#ifndef VFS_H
+#define VFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VFS_OK = 0,
+    VFS_E_INVALID = -1,     /* bad argument: null pointer, size, pitch, count */
+    VFS_E_NOMEM = -2,       /* device allocation failed */
+    VFS_E_BUDGET = -3,      /* request exceeds a configured memory budget */
+    VFS_E_MODEL = -4,       /* camera model not invertible on its field of view */
+    VFS_E_DEGENERATE = -5,  /* zero baseline: no trajectory field (Sec. III-B needs |t| != 0) */
+    VFS_E_DEVICE = -6       /* a HIP runtime call failed */
+} vfs_status;
+
+typedef enum { VFS_PINHOLE = 0, VFS_EQUIDISTANT = 1, VFS_KANNALA_BRANDT = 2 } vfs_model;
+typedef enum { VFS_TGV = 0, VFS_TV = 1 } vfs_reg;
+typedef enum { VFS_F32 = 0 } vfs_storage;
+
+/* Camera: r_d(theta) = theta + k1 theta^3 + k2 theta^5 + k3 theta^7 +
+ * k4 theta^9 (Kannala-Brandt; equidistant is k = 0; pinhole r_d = tan theta),
+ * pixel = (cx, cy) + (fx, fy) r_d (cos phi, sin phi).  fov_deg is the full
+ * field of view of the circular mask of Sec. IV-B. */
+typedef struct {
+    int model;             /* vfs_model */
+    int width, height;
+    double fx, fy, cx, cy;
+    double k[4];
+    double fov_deg;
+} vfs_camera;
+
+/* Solver parameters.  Defaults (vfs_params_default) are the values printed
+ * in Sec. IV-C: alpha0 = 17, alpha1 = 1.2, beta = 9, eta = 0.85, and the
+ * 0.2 px clip of Sec. III-C; lambda (not printed) defaults to 50;
+ * theta_gamma = 0 selects the constant over-relaxation theta = 1, > 0 the
+ * accelerated schedule theta_k = 1/sqrt(1 + 2 gamma s_k) on the scalar
+ * factor s_k of the preconditioned steps. */
+typedef struct {
+    int levels, warps, iters;  /* pyramid levels (scale 1/2), warps per level, primal-dual iterations per warp */
+    int reg;                   /* vfs_reg: TGV-L1 of Eq. (10), or TV-L1 (v = 0) */
+    double lambda, alpha0, alpha1, beta, eta, du_max, theta_gamma;
+    int storage;               /* vfs_storage */
+} vfs_params;
+
+typedef struct vfs_rig vfs_rig;
+
+/* Fill *out with the defaults above and levels = 5, warps = 10, iters = 100. */
+vfs_status vfs_params_default(vfs_params* out);
+
+/* Rig set-up, once per calibration and resolution (Sec. III-B, Sec. IV-A,
+ * Sec. IV-B).  cam0 and cam1 (host) must have equal width and height, both
+ * divisible by 2^(levels-1); R (host, 9 doubles, row-major) and t (host, 3
+ * doubles) give X1 = R X0 + t.  Computes in double precision on the device,
+ * for every level l: the trajectory field gamma'_l (unit tangents of the
+ * epipolar curves of the pre-rotated pair, by projecting the unit sphere
+ * into camera 0 and into camera 0 moved by a vanishing step along
+ * t' = R^T t), the circular mask M_l (nearest-neighbour scaled), the
+ * epipole guard (2 degrees around +-t'), and at level 0 the calibration
+ * field c(x) = pi1(R r0(x)) - pi0(r0(x)).  The rig keeps them in device
+ * memory.  Synchronises hip_stream before returning.
+ * Errors: VFS_E_INVALID, VFS_E_MODEL (radial map not increasing on
+ * [0, FOV/2], or pinhole FOV >= 180), VFS_E_DEGENERATE (t = 0),
+ * VFS_E_NOMEM, VFS_E_DEVICE. */
+vfs_status vfs_rig_create(const vfs_camera* cam0, const vfs_camera* cam1, const double R[9],
+                          const double t[3], int levels, void* hip_stream, vfs_rig** out);
+
+void vfs_rig_destroy(vfs_rig* rig);
+
+/* Copy a rig field of one level into dst (device), rows of pitch_bytes:
+ *   which = 0: trajectory field, float32 pairs (gx, gy) per pixel;
+ *   which = 1: calibration field (level 0 only), float32 pairs;
+ *   which = 2: flags, one byte per pixel: bit0 mask M, bit1 mx (M at P and
+ *              P+x), bit2 my, bit3 data term on (mask, inside camera 1's
+ *              view after pre-rotation, not near an epipole), bit4 epipole.
+ * Errors: VFS_E_INVALID (level / which / pitch), VFS_E_DEVICE. */
+vfs_status vfs_rig_field(const vfs_rig* rig, int level, int which, void* dst, size_t pitch_bytes,
+                         void* hip_stream);
+
+/* Whole method on n image pairs of one rig (Algorithm 1 in the pyramid of
+ * Sec. IV-B, after the pre-rotation of Sec. IV-A, then triangulation).
+ * I0[b], I1[b] (device) are H x W float32 images with row pitch
+ * pitch_bytes; outputs (device, row pitch pitch_bytes for u/depth/z,
+ * 2*pitch_bytes for w, pitch_bytes/4 for valid) per pair b:
+ *   u_out[b]     displacement along the epipolar curve (level-0 pixels),
+ *   w_out[b]     warping vectors, float32 pairs (wx, wy),
+ *   depth_out[b] range along the camera-0 ray (+inf where invalid),
+ *   z_out[b]     its z coordinate (may be NULL),
+ *   valid_out[b] 1 where the depth is valid (may be NULL).
+ * betas / etas (host, n doubles each, may be NULL): per-pair tensor
+ * parameters overriding params->beta / eta (Eq. (12)).  params (host) must
+ * have params->levels equal to the rig's.  The library keeps one device
+ * workspace per rig, grown on demand (allocation happens here, outside the
+ * enqueued work); n <= VFS_MAX_BATCH.
+ * Errors: VFS_E_INVALID, VFS_E_NOMEM, VFS_E_DEVICE. */
+#define VFS_MAX_BATCH 32
+vfs_status vfs_solve_batch(vfs_rig* rig, int n, const float* const* I0, const float* const* I1,
+                           size_t pitch_bytes, float* const* u_out, float* const* w_out,
+                           float* const* depth_out, float* const* z_out, uint8_t* const* valid_out,
+                           const vfs_params* params, const double* betas, const double* etas,
+                           void* hip_stream);
+
+/* One pair: vfs_solve_batch with n = 1. */
+vfs_status vfs_solve(vfs_rig* rig, const float* I0, const float* I1, size_t pitch_bytes, float* u_out,
+                     float* w_out, float* depth_out, float* z_out, uint8_t* valid_out,
+                     const vfs_params* params, void* hip_stream);
+
+/* ---- Steps of the method on caller buffers (device), for step-by-step use
+ * and testing.  Layout: row-major with a common row pitch of `pitch`
+ * ELEMENTS (not bytes) for every plane; vector planes interleave their
+ * components (float2 (x, y) per pixel for w, gamma, v, p; float4 for q and
+ * for the tensor pack (t11, t12, t22, I_u)).  flags as in vfs_rig_field. */
+
+/* Eq. (12): tensor from the level image J0 and the flags (mask bit), written
+ * to tpack.xyz (tpack.w untouched).  Central differences, one-sided where a
+ * neighbour leaves the image or the mask; T = I where the gradient is below
+ * 1e-12 or the pixel is masked out. */
+vfs_status vfs_step_tensor(int width, int height, size_t pitch, const float* J0, const uint8_t* flags,
+                           double beta, double eta, float* tpack, void* hip_stream);
+
+/* Eqs. (3), (5), Sec. III-B, Algorithm 1: with clip != 0 first clip and
+ * accumulate the previous warp (du = clamp(u - u_w, +-du_max), u = u_w + du,
+ * w += du gamma_w); then (unless clip_only) linearise at y = x + w:
+ * gamma_w = normalised bicubic (Keys, a = -1/2) sample of the trajectory
+ * field, I_u = I1(y + gamma_w) - I1(y) into tpack.w, rho_c = I1(y) - I0(x)
+ * - u I_u, both 0 where the data term is off (flags bit3); u_w = u. */
+vfs_status vfs_step_linearise(int width, int height, size_t pitch, const float* J0, const float* J1,
+                              const float* gamma, const uint8_t* flags, float* u, float* u_w, float* w,
+                              float* gamma_w, float* tpack, float* rho, int clip, int clip_only,
+                              double du_max, void* hip_stream);
+
+/* Eq. (11): `iters` primal-dual iterations from a warp start (ubar = u,
+ * vbar = v), with the preconditioned steps of Sec. III-D recomputed from
+ * tpack and flags, the resolvent of Eq. (13), and theta per
+ * params->theta_gamma.  u, v, p, q are read and overwritten; scratch_* are
+ * caller buffers of the same shapes used as the second copy of the state
+ * (the iteration reads one copy and writes the other).  TV mode ignores v, q
+ * and their scratch (may be NULL). */
+vfs_status vfs_step_pd(int width, int height, size_t pitch, const float* tpack, const float* rho,
+                       const uint8_t* flags, float* u, float* v, float* p, float* q, float* scratch_u,
+                       float* scratch_v, float* scratch_p, float* scratch_q, const vfs_params* params,
+                       int iters, void* hip_stream);
+
+/* Sec. IV-B: mask-aware x2 bilinear upsampling of (u, w) from a coarse level
+ * (width_c x height_c, pitch_c elements, mask = flags_c bit0) to the fine
+ * level (2 width_c x 2 height_c, pitch_f), multiplied by 2. */
+vfs_status vfs_step_upsample(int width_c, int height_c, size_t pitch_c, const uint8_t* flags_c,
+                             const float* u_c, const float* w_c, size_t pitch_f, float* u_f, float* w_f,
+                             void* hip_stream);
+
+/* Sec. III-D: triangulate level-0 warping vectors w of a rig (closest
+ * approach of the rays pi0^-1(x) and pi0^-1(x + w) from -t'), in double
+ * precision.  Outputs as in vfs_solve_batch. */
+vfs_status vfs_step_triangulate(const vfs_rig* rig, size_t pitch, const float* w, float* depth, float* z,
+                                uint8_t* valid, void* hip_stream);
+
+/* ---- Measurement: when enabled, vfs_solve_batch records HIP events on its
+ * stream around the primal-dual launches of level 0 and accumulates their
+ * elapsed time.  vfs_profile_read synchronises the stream of the last solve
+ * and returns the accumulated milliseconds and the number of level-0
+ * primal-dual launches (counts since the last reset). */
+vfs_status vfs_profile_enable(vfs_rig* rig, int enable);
+vfs_status vfs_profile_read(vfs_rig* rig, double* pd0_ms, long long* pd0_launches, int reset);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* vfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VFS_H */

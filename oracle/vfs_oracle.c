@@ -193,6 +193,7 @@ void or_mask0(const or_camera *c, unsigned char *m)
 {
     int W = c->width, H = c->height;
     double rmax = or_theta_d(c, 0.5 * c->fov_deg * OR_PI / 180.0);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < H; ++i)
         for (int j = 0; j < W; ++j) {
             double mx = (j - c->cx) / c->fx, my = (i - c->cy) / c->fy;
@@ -222,6 +223,7 @@ void or_calibration_field(const or_camera *c0, const or_camera *c1, const double
     int W = c0->width, H = c0->height;
     double lim0 = or_theta_limit(c0);
     double half1 = 0.5 * c1->fov_deg * OR_PI / 180.0;
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < H; ++i)
         for (int j = 0; j < W; ++j) {
             double r0[3], X1[3], x0[2], x1[2];

@@ -1,0 +1,232 @@
+"""ctypes binding of libvfs.so (the C ABI of include/vfs.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvfs.so")
+
+FIELD_TRAJECTORY, FIELD_CALIBRATION, FIELD_FLAGS = 0, 1, 2
+F_MASK, F_MX, F_MY, F_DATA, F_EPI = 1, 2, 4, 8, 16
+MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2, "kannala_brandt": 2}
+REGS = {"tgv": 0, "tv": 1}
+STATUS = {0: "VFS_OK", -1: "VFS_E_INVALID", -2: "VFS_E_NOMEM", -3: "VFS_E_BUDGET", -4: "VFS_E_MODEL",
+          -5: "VFS_E_DEGENERATE", -6: "VFS_E_DEVICE"}
+
+
+class VfsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int), ("width", ctypes.c_int), ("height", ctypes.c_int),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("k", ctypes.c_double * 4), ("fov_deg", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("warps", ctypes.c_int), ("iters", ctypes.c_int),
+                ("reg", ctypes.c_int), ("lam", ctypes.c_double), ("alpha0", ctypes.c_double),
+                ("alpha1", ctypes.c_double), ("beta", ctypes.c_double), ("eta", ctypes.c_double),
+                ("du_max", ctypes.c_double), ("theta_gamma", ctypes.c_double), ("storage", ctypes.c_int)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1909_07545_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.vfs_last_error.restype = ctypes.c_char_p
+        L.vfs_rig_create.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp]
+        L.vfs_rig_destroy.argtypes = [_vp]
+        L.vfs_rig_destroy.restype = None
+        L.vfs_rig_field.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]
+        L.vfs_solve_batch.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp,
+                                      _vp, _vp, _vp, _vp]
+        L.vfs_solve.argtypes = [_vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.vfs_step_tensor.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _vp, _vp, ctypes.c_double,
+                                      ctypes.c_double, _vp, _vp]
+        L.vfs_step_linearise.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t] + [_vp] * 10 + \
+            [ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp]
+        L.vfs_step_pd.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t] + [_vp] * 11 + \
+            [_vp, ctypes.c_int, _vp]
+        L.vfs_step_upsample.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _vp, _vp, _vp,
+                                        ctypes.c_size_t, _vp, _vp, _vp]
+        L.vfs_step_triangulate.argtypes = [_vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
+        L.vfs_profile_enable.argtypes = [_vp, ctypes.c_int]
+        L.vfs_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+        L.vfs_params_default.argtypes = [_vp]
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise VfsError(st, lib().vfs_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _camera(c: dict) -> Camera:
+    m = c["model"]
+    return Camera(MODELS[m] if isinstance(m, str) else int(m), int(c["width"]), int(c["height"]),
+                  float(c["fx"]), float(c["fy"]), float(c["cx"]), float(c["cy"]),
+                  (ctypes.c_double * 4)(*[float(x) for x in c.get("k", (0.0,) * 4)]), float(c["fov_deg"]))
+
+
+def default_params() -> dict:
+    p = Params()
+    _check(lib().vfs_params_default(ctypes.byref(p)))
+    return dict(levels=p.levels, warps=p.warps, iters=p.iters, reg="tgv" if p.reg == 0 else "tv",
+                alpha0=p.alpha0, alpha1=p.alpha1, beta=p.beta, eta=p.eta, du_max=p.du_max,
+                theta_gamma=p.theta_gamma, storage=p.storage, **{"lambda": p.lam})
+
+
+def _params(d: dict) -> Params:
+    reg = d.get("reg", "tgv")
+    return Params(int(d["levels"]), int(d["warps"]), int(d["iters"]),
+                  REGS[reg] if isinstance(reg, str) else int(reg), float(d["lambda"]), float(d["alpha0"]),
+                  float(d["alpha1"]), float(d["beta"]), float(d["eta"]), float(d["du_max"]),
+                  float(d.get("theta_gamma", 0.0)), int(d.get("storage", 0)))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev_f32(t, shape=None):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class Rig:
+    """Trajectory / calibration fields and masks of one calibration (vfs_rig_create)."""
+
+    def __init__(self, cam0: dict, cam1: dict, R, t, levels: int, stream=None):
+        self._h = ctypes.c_void_p()
+        c0, c1 = _camera(cam0), _camera(cam1)
+        Rr = (ctypes.c_double * 9)(*np.asarray(R, np.float64).reshape(9).tolist())
+        tt = (ctypes.c_double * 3)(*np.asarray(t, np.float64).reshape(3).tolist())
+        _check(lib().vfs_rig_create(ctypes.byref(c0), ctypes.byref(c1), Rr, tt, int(levels), _stream(stream),
+                                    ctypes.byref(self._h)))
+        self.cam0, self.cam1, self.levels = dict(cam0), dict(cam1), int(levels)
+        self.width, self.height = int(cam0["width"]), int(cam0["height"])
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().vfs_rig_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def field(self, level: int, which: int, stream=None) -> torch.Tensor:
+        H, W = self.height >> level, self.width >> level
+        if which == FIELD_FLAGS:
+            out = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+            pitch = W
+        else:
+            out = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
+            pitch = 8 * W
+        _check(lib().vfs_rig_field(self._h, int(level), int(which), _ptr(out), pitch, _stream(stream)))
+        return out
+
+
+def solve_batch(rig: Rig, I0s, I1s, params: dict, betas=None, etas=None, stream=None, out=None):
+    """Whole method on a batch of pairs (vfs_solve_batch).  Inputs: lists of
+    (H, W) float32 CUDA tensors.  Returns a list of dicts of output tensors
+    (u, w, depth, z, valid); ``out`` may pass pre-allocated ones."""
+    n = len(I0s)
+    H, W = rig.height, rig.width
+    for t in list(I0s) + list(I1s):
+        _dev_f32(t, (H, W))
+    if out is None:
+        out = [dict(u=torch.empty((H, W), device="cuda"), w=torch.empty((H, W, 2), device="cuda"),
+                    depth=torch.empty((H, W), device="cuda"), z=torch.empty((H, W), device="cuda"),
+                    valid=torch.empty((H, W), dtype=torch.uint8, device="cuda")) for _ in range(n)]
+    arr = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])  # noqa: E731
+    p = _params(params)
+    bet = (ctypes.c_double * n)(*betas) if betas is not None else None
+    et = (ctypes.c_double * n)(*etas) if etas is not None else None
+    _check(lib().vfs_solve_batch(rig.handle, n, arr(I0s), arr(I1s), 4 * W, arr([o["u"] for o in out]),
+                                 arr([o["w"] for o in out]), arr([o["depth"] for o in out]),
+                                 arr([o["z"] for o in out]), arr([o["valid"] for o in out]), ctypes.byref(p),
+                                 bet, et, _stream(stream)))
+    return out
+
+
+def solve(rig: Rig, I0, I1, params: dict, stream=None):
+    return solve_batch(rig, [I0], [I1], params, stream=stream)[0]
+
+
+def step_tensor(J0, flags, beta: float, eta: float, tpack, stream=None):
+    H, W = J0.shape
+    _check(lib().vfs_step_tensor(W, H, W, _ptr(J0), _ptr(flags), float(beta), float(eta), _ptr(tpack),
+                                 _stream(stream)))
+
+
+def step_linearise(J0, J1, gamma, flags, u, u_w, w, gamma_w, tpack, rho, clip: bool, clip_only: bool,
+                   du_max: float, stream=None):
+    H, W = J0.shape
+    _check(lib().vfs_step_linearise(W, H, W, _ptr(J0), _ptr(J1), _ptr(gamma), _ptr(flags), _ptr(u), _ptr(u_w),
+                                    _ptr(w), _ptr(gamma_w), _ptr(tpack), _ptr(rho), int(clip), int(clip_only),
+                                    float(du_max), _stream(stream)))
+
+
+def step_pd(tpack, rho, flags, u, v, p, q, params: dict, iters: int, stream=None):
+    H, W = u.shape
+    su, sp = torch.empty_like(u), torch.empty_like(p)
+    sv = torch.empty_like(v) if v is not None else None
+    sq = torch.empty_like(q) if q is not None else None
+    pp = _params(params)
+    _check(lib().vfs_step_pd(W, H, W, _ptr(tpack), _ptr(rho), _ptr(flags), _ptr(u), _ptr(v), _ptr(p), _ptr(q),
+                             _ptr(su), _ptr(sv), _ptr(sp), _ptr(sq), ctypes.byref(pp), int(iters),
+                             _stream(stream)))
+
+
+def step_upsample(flags_c, u_c, w_c, u_f, w_f, stream=None):
+    Hc, Wc = u_c.shape
+    _check(lib().vfs_step_upsample(Wc, Hc, Wc, _ptr(flags_c), _ptr(u_c), _ptr(w_c), 2 * Wc, _ptr(u_f), _ptr(w_f),
+                                   _stream(stream)))
+
+
+def step_triangulate(rig: Rig, w, depth, z=None, valid=None, stream=None):
+    _check(lib().vfs_step_triangulate(rig.handle, rig.width, _ptr(w), _ptr(depth), _ptr(z), _ptr(valid),
+                                      _stream(stream)))
+
+
+def profile_enable(rig: Rig, on: bool = True):
+    _check(lib().vfs_profile_enable(rig.handle, int(on)))
+
+
+def profile_read(rig: Rig, reset: bool = True):
+    ms = ctypes.c_double()
+    n = ctypes.c_longlong()
+    _check(lib().vfs_profile_read(rig.handle, ctypes.byref(ms), ctypes.byref(n), int(reset)))
+    return ms.value, n.value

@@ -1,0 +1,87 @@
+"""The C ABI library: it loads without a GPU, exports every entry point that
+include/vfs.h declares, and rejects bad arguments before any device work
+(these calls return before the first HIP runtime call, so they run on the
+CPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vfs.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(vfs_[a-z0-9_]+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def vfs():
+    from paper_1909_07545_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libvfs.so not built (run __graft_entry__.build())")
+    return _lib
+
+
+def test_exports_every_declared_symbol(vfs):
+    names = _declared()
+    assert len(names) >= 14
+    L = ctypes.CDLL(vfs.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_params_default_are_the_paper_values(vfs):
+    import json
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_parameters.json")))
+    d = vfs.default_params()
+    assert (d["alpha0"], d["alpha1"], d["beta"], d["eta"], d["du_max"]) == \
+        (g["alpha0"], g["alpha1"], g["beta"], g["eta"], g["du_max_px"])
+    assert d["reg"] == "tgv" and d["theta_gamma"] == 0.0
+
+
+CAM = dict(model="kb", width=64, height=48, fx=20.0, fy=20.0, cx=31.5, cy=23.5, k=(0.01, -0.005, 0.0, 0.0),
+           fov_deg=180.0)
+
+
+def _create(vfs, cam0=CAM, cam1=CAM, R=np.eye(3), t=(0.1, 0, 0), levels=3):
+    L = vfs.lib()
+    c0, c1 = vfs._camera(cam0), vfs._camera(cam1)
+    Rr = (ctypes.c_double * 9)(*np.asarray(R, float).reshape(9))
+    tt = (ctypes.c_double * 3)(*np.asarray(t, float))
+    h = ctypes.c_void_p()
+    st = L.vfs_rig_create(ctypes.byref(c0), ctypes.byref(c1), Rr, tt, levels, None, ctypes.byref(h))
+    return st, L.vfs_last_error().decode()
+
+
+def test_rig_create_rejects_bad_arguments(vfs):
+    assert _create(vfs, t=(0.0, 0.0, 0.0))[0] == -5                                 # zero baseline
+    assert _create(vfs, cam0=dict(CAM, k=(0, 0, 0, -0.05), fov_deg=200))[0] == -4   # non-monotone r_d
+    assert _create(vfs, cam0=dict(CAM, model="pinhole", fov_deg=180))[0] == -4
+    assert _create(vfs, cam1=dict(CAM, width=32))[0] == -1                          # size mismatch
+    assert _create(vfs, levels=6)[0] == -1                                          # 48 not divisible by 32
+    assert _create(vfs, levels=0)[0] == -1
+    assert _create(vfs, cam0=dict(CAM, fx=0.0))[0] == -1
+    st, msg = _create(vfs, t=(0.0, 0.0, 0.0))
+    assert "baseline" in msg
+    L = vfs.lib()
+    assert L.vfs_rig_create(None, None, None, None, 3, None, None) == -1
+
+
+def test_solve_and_steps_reject_bad_arguments(vfs):
+    L = vfs.lib()
+    p = vfs._params(dict(vfs.default_params(), levels=3))
+    one = (ctypes.c_void_p * 1)(1)
+    assert L.vfs_solve_batch(None, 1, one, one, 256, one, one, one, None, None, ctypes.byref(p), None, None,
+                             None) == -1
+    assert L.vfs_step_tensor(0, 4, 4, one, one, 9.0, 0.85, one, None) == -1
+    assert L.vfs_step_tensor(8, 4, 4, one, one, 9.0, 0.85, one, None) == -1           # pitch < width
+    bad = vfs._params(dict(vfs.default_params(), alpha1=0.0))
+    assert L.vfs_step_pd(8, 8, 8, one, one, one, one, one, one, one, one, one, one, one, ctypes.byref(bad), 3,
+                         None) == -1
+    assert L.vfs_step_upsample(4, 4, 2, one, one, one, 8, one, one, None) == -1
+    assert L.vfs_profile_enable(None, 1) == -1

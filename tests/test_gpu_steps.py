@@ -1,0 +1,246 @@
+"""GPU parity of each step of the method against the FP64 oracle, on the
+same seeded inputs (the oracle receives the float32 values the GPU gets).
+
+Sizes: C1 (128x128), a ragged 200x136 rig (neither dimension a multiple of
+the primal-dual tile of 62 columns x 64 rows), and the full 2048x2048 level 0
+of the batched 200-degree configuration.  Tolerances are the FP32 rounding of
+each step (stated per test).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import configs, scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vfs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1909_07545_amd as v
+    return v
+
+
+def _t(a, dtype=None):
+    import torch
+    a = np.ascontiguousarray(a)
+    t = torch.from_numpy(a if dtype is None else a.astype(dtype))
+    return t.cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def f32(a):
+    """The float32 value the GPU receives, as float64 for the oracle."""
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+_FLAGS = {}
+
+
+def oracle_flags(rig, level):
+    key = (id(rig), level)
+    if key not in _FLAGS:
+        _FLAGS[key] = _oracle_flags(rig, level)
+    return _FLAGS[key]
+
+
+def _oracle_flags(rig, level):
+    cam0, cam1, R, t = rig["cam0"], rig["cam1"], rig["R"], rig["t"]
+    m = oracle.level_mask(oracle.mask0(cam0), level).astype(np.uint8)
+    mx = np.zeros_like(m)
+    my = np.zeros_like(m)
+    mx[:, :-1] = m[:, :-1] & m[:, 1:]
+    my[:-1, :] = m[:-1, :] & m[1:, :]
+    dv = oracle.data_valid(cam0, cam1, R, t, level)
+    _, epi = oracle.trajectory_field(cam0, R, t, level)
+    return (m | (mx << 1) | (my << 2) | (dv << 3) | (epi << 4)).astype(np.uint8)
+
+
+RIGS = ["c1", "r200", "c2", "c5"]
+
+
+_RIGS = {}
+
+
+def _rig(cid):
+    if cid not in _RIGS:
+        _RIGS[cid] = scene.make_rig(configs.get(cid))
+    return _RIGS[cid]
+
+
+@pytest.mark.parametrize("cid", RIGS)
+def test_rig_fields(vfs, cid):
+    """Flags bit-exact; trajectory field and calibration field within float32
+    rounding of the FP64 values."""
+    rig = _rig(cid)
+    cfg = configs.get(cid)
+    R = vfs.Rig(rig["cam0"], rig["cam1"], rig["R"], rig["t"], cfg["levels"])
+    for l in range(cfg["levels"]):
+        fl = _np(R.field(l, vfs.FIELD_FLAGS))
+        assert np.array_equal(fl, oracle_flags(rig, l)), f"level {l}"
+        g = _np(R.field(l, vfs.FIELD_TRAJECTORY))
+        go, _ = oracle.trajectory_field(rig["cam0"], rig["R"], rig["t"], l)
+        assert np.max(np.abs(g - go)) < 1e-6, f"level {l}"
+    c = _np(R.field(0, vfs.FIELD_CALIBRATION))
+    co, _ = oracle.calibration_field(rig["cam0"], rig["cam1"], rig["R"])
+    assert np.max(np.abs(c - co)) < 2e-5
+
+
+def _smooth_image(H, W, seed, lo=0.1, hi=0.9):
+    rng = np.random.default_rng(seed)
+    jj, ii = np.meshgrid(np.arange(W), np.arange(H))
+    s = np.zeros((H, W))
+    for _ in range(12):
+        k = rng.uniform(0.01, 0.3, 2) * rng.choice([-1, 1], 2)
+        s += np.cos(k[0] * jj + k[1] * ii + rng.uniform(0, 6.3)) / np.linalg.norm(k)
+    s = (s - s.min()) / (s.max() - s.min())
+    return (lo + (hi - lo) * s + 0.01 * rng.normal(size=(H, W))).astype(np.float32)
+
+
+def _level_inputs(cid, level, seed=0):
+    rig = _rig(cid)
+    H, W = rig["cam0"]["height"] >> level, rig["cam0"]["width"] >> level
+    flags = oracle_flags(rig, level)
+    J0 = _smooth_image(H, W, seed)
+    J1 = _smooth_image(H, W, seed + 1)
+    gam, _ = oracle.trajectory_field(rig["cam0"], rig["R"], rig["t"], level)
+    return rig, flags, J0, J1, gam.astype(np.float32)
+
+
+@pytest.mark.parametrize("cid,level", [("c1", 0), ("r200", 0), ("c2", 1), ("c5", 0)])
+def test_tensor(vfs, cid, level):
+    """Eq. (12) on the level image: float32 vs FP64 within 2e-6."""
+    import torch
+    rig, flags, J0, _, _ = _level_inputs(cid, level)
+    H, W = J0.shape
+    tp = torch.zeros((H, W, 4), device="cuda")
+    for beta, eta in ((9.0, 0.85), (11.3, 0.72)):
+        vfs.step_tensor(_t(J0), _t(flags), beta, eta, tp)
+        To = oracle.tensor(f32(J0), flags & 1, beta, eta)
+        assert np.max(np.abs(_np(tp)[..., :3] - To)) < 2e-6
+
+
+@pytest.mark.parametrize("cid,level", [("c1", 0), ("r200", 0), ("c2", 1), ("c5", 0)])
+def test_linearise_and_clip(vfs, cid, level):
+    """Eqs. (3), (5) at the warped point, with the clip and accumulation of
+    the previous warp: u, u_w, w, gamma_w, I_u, rho_c within 5e-6."""
+    import torch
+    rig, flags, J0, J1, gam = _level_inputs(cid, level, seed=3)
+    H, W = J0.shape
+    rng = np.random.default_rng(4)
+    jj, ii = np.meshgrid(np.arange(W), np.arange(H))
+    u_w = (2.0 + np.sin(0.05 * jj) * np.cos(0.04 * ii)).astype(np.float32)
+    u = (u_w + rng.uniform(-0.5, 0.5, (H, W))).astype(np.float32)
+    w = (u_w[..., None] * gam + rng.uniform(-0.3, 0.3, (H, W, 2))).astype(np.float32)
+    gw = gam.copy()
+    tu, tuw, tw, tgw = _t(u), _t(u_w), _t(w), _t(gw)
+    tp = torch.zeros((H, W, 4), device="cuda")
+    rho = torch.zeros((H, W), device="cuda")
+    vfs.step_linearise(_t(J0), _t(J1), _t(gam), _t(flags), tu, tuw, tw, tgw, tp, rho, True, False, 0.2)
+    uo, wo = oracle.clip_accumulate(0.2, f32(u_w), f32(gw), f32(u), f32(w))
+    uwo, gwo, Iuo, rhoo = oracle.linearise(f32(J0), f32(J1), f32(gam), (flags >> 3) & 1, uo, wo)
+    assert np.max(np.abs(_np(tu) - uo)) < 5e-6
+    assert np.max(np.abs(_np(tw) - wo)) < 5e-6
+    assert np.max(np.abs(_np(tuw) - uwo)) < 5e-6
+    # renormalising a short bicubic sample (next to an epipole guard) scales its rounding
+    assert np.max(np.abs(_np(tgw) - gwo)) < 5e-5
+    assert np.max(np.abs(_np(tp)[..., 3] - Iuo)) < 5e-6
+    assert np.max(np.abs(_np(rho) - rhoo)) < 5e-5
+
+
+def _pd_state(cid, level, tgv=True, seed=5):
+    rig, flags, J0, _, _ = _level_inputs(cid, level, seed=seed)
+    H, W = J0.shape
+    m = flags & 1
+    T = oracle.tensor(f32(J0), m, 9.0, 0.85).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    Iu = (rng.normal(0, 0.05, (H, W)) * ((flags >> 3) & 1)).astype(np.float32)
+    rho = (rng.normal(0, 0.05, (H, W)) * ((flags >> 3) & 1)).astype(np.float32)
+    u = (1.5 + 0.3 * rng.random((H, W))).astype(np.float32)
+    v = (0.05 * rng.normal(size=(H, W, 2)) * m[..., None]).astype(np.float32)
+    p = oracle.project_balls(0.7 * rng.normal(size=(H, W, 2)), 2).reshape(H, W, 2) * m[..., None]
+    q = oracle.project_balls(0.7 * rng.normal(size=(H, W, 4)), 4).reshape(H, W, 4) * m[..., None]
+    return flags, T, Iu, rho, u, v, p.astype(np.float32), q.astype(np.float32)
+
+
+@pytest.mark.parametrize("cid,level,K,reg,tg", [
+    ("c1", 0, 1, "tgv", 0.0), ("c1", 0, 2, "tgv", 0.0), ("c1", 0, 50, "tgv", 0.0),
+    ("r200", 0, 7, "tgv", 0.0), ("r200", 0, 50, "tv", 0.0), ("c1", 1, 30, "tgv", 0.3),
+    ("c2", 0, 20, "tgv", 0.0), ("c5", 0, 3, "tgv", 0.0)])
+def test_primal_dual(vfs, cid, level, K, reg, tg):
+    """K iterations of Eq. (11) from a warp start: u, v, p, q within 2e-5 of
+    the FP64 oracle (float32 accumulates ~1e-7 per iteration)."""
+    import torch
+    tgv = reg == "tgv"
+    flags, T, Iu, rho, u, v, p, q = _pd_state(cid, level, tgv)
+    H, W = u.shape
+    params = dict(configs.PAPER_PARAMS, levels=1, warps=1, iters=K, reg=reg, theta_gamma=tg)
+    tpack = np.concatenate([T, Iu[..., None]], -1).astype(np.float32)
+    tu, tp = _t(u), _t(p)
+    tv, tq = (_t(v), _t(q)) if tgv else (None, None)
+    vfs.step_pd(_t(tpack), _t(rho), _t(flags), tu, tv, tp, tq, params, K)
+    torch.cuda.synchronize()
+    m = flags & 1
+    sp, su, sv = oracle.steps(f32(T), m, params["alpha0"], params["alpha1"], reg)
+    st = oracle.pd_iterations(params, f32(T), m, sp, su, sv, f32(Iu), f32(rho), f32(u), f32(v), f32(p), f32(q), K)
+    tol = 2e-5
+    assert np.max(np.abs(_np(tu) - st["u"])) < tol
+    assert np.max(np.abs(_np(tp) - st["p"])) < tol
+    if tgv:
+        assert np.max(np.abs(_np(tv) - st["v"])) < tol
+        assert np.max(np.abs(_np(tq) - st["q"])) < tol
+
+
+@pytest.mark.parametrize("cid,level", [("c1", 1), ("r200", 1), ("c5", 1)])
+def test_upsample(vfs, cid, level):
+    """Mask-aware x2 transfer of (u, w) (Sec. IV-B): within 2e-6."""
+    import torch
+    rig = _rig(cid)
+    flags_c = oracle_flags(rig, level)
+    Hc, Wc = flags_c.shape
+    rng = np.random.default_rng(6)
+    uc = rng.uniform(0, 4, (Hc, Wc)).astype(np.float32)
+    wc = rng.uniform(-4, 4, (Hc, Wc, 2)).astype(np.float32)
+    uf = torch.zeros((2 * Hc, 2 * Wc), device="cuda")
+    wf = torch.zeros((2 * Hc, 2 * Wc, 2), device="cuda")
+    vfs.step_upsample(_t(flags_c), _t(uc), _t(wc), uf, wf)
+    uo, wo = oracle.upsample(flags_c & 1, f32(uc), f32(wc))
+    assert np.max(np.abs(_np(uf) - uo)) < 2e-6
+    assert np.max(np.abs(_np(wf) - wo)) < 2e-6
+
+
+@pytest.mark.parametrize("cid", ["c2", "c5"])
+def test_triangulate(vfs, cid):
+    """Closest-approach depth in double precision from the same float32 warp
+    vectors: valid flags identical, depth and Z within float32 rounding."""
+    import torch
+    rig = _rig(cid)
+    cfg = configs.get(cid)
+    cam = rig["cam0"]
+    H, W = cam["height"], cam["width"]
+    R = vfs.Rig(rig["cam0"], rig["cam1"], rig["R"], rig["t"], cfg["levels"])
+    gam, _ = oracle.trajectory_field(cam, rig["R"], rig["t"], 0)
+    rng = np.random.default_rng(7)
+    w = (gam * rng.uniform(-0.5, 6.0, (H, W, 1))).astype(np.float32)
+    depth = torch.zeros((H, W), device="cuda")
+    z = torch.zeros((H, W), device="cuda")
+    valid = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+    vfs.step_triangulate(R, _t(w), depth, z, valid)
+    dv = oracle.data_valid(cam, rig["cam1"], rig["R"], rig["t"], 0)
+    do, zo, vo = oracle.triangulate(cam, rig["R"], rig["t"], f32(w), dv)
+    vg = _np(valid).astype(bool)
+    assert np.array_equal(vg, vo)
+    # where the rays meet at a usable angle (|w| >= 0.05 px) the double-precision
+    # results agree to float32 output rounding; closer to parallel rays the
+    # range is ill-conditioned (1 - (a.b)^2 -> 1e-12) and only validity is compared
+    ok = vo & (np.linalg.norm(w, axis=-1) >= 0.05)
+    assert ok.sum() > 0.5 * vo.sum()
+    rel = np.abs(_np(depth)[ok] - do[ok]) / do[ok]
+    assert np.max(rel) < 1e-6
+    assert np.max(np.abs(_np(z)[ok] - zo[ok]) / do[ok]) < 1e-6
+    assert np.all(np.isinf(_np(depth)[~vo]))
