@@ -189,10 +189,11 @@ vfs_status vfs_step_triangulate(const vfs_rig* rig, size_t pitch, const float* w
                                 uint8_t* valid, void* hip_stream);
 
 /* ---- Measurement: when enabled, vfs_solve_batch records HIP events on its
- * stream around the primal-dual launches of level 0 and accumulates their
- * elapsed time.  vfs_profile_read synchronises the stream of the last solve
- * and returns the accumulated milliseconds and the number of level-0
- * primal-dual launches (counts since the last reset). */
+ * stream around the level-0 primal-dual launches that each carry two
+ * iterations of Eq. (11) (the dominant kernel) and accumulates their elapsed
+ * time.  vfs_profile_read synchronises the stream of the last solve and
+ * returns the accumulated milliseconds and the number of those launches
+ * (counts since the last reset). */
 vfs_status vfs_profile_enable(vfs_rig* rig, int enable);
 vfs_status vfs_profile_read(vfs_rig* rig, double* pd0_ms, long long* pd0_launches, int reset);
 

@@ -227,11 +227,12 @@ vfs_status check_params(const vfs_params* p)
 }
 
 // K primal-dual iterations from a warp start on the state index pair (iu, ip);
-// returns the indices holding the result.
-void run_pd(PdArgs base, const Sched& sc, int K, float* const* u, float2* const* v, float2* const* p,
-            float4* const* q, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+// the indices are updated to those holding the result.  Returns the number of
+// two-iteration launches, which ev0 / ev1 (if given) bracket.
+int run_pd(PdArgs base, const Sched& sc, int K, float* const* u, float2* const* v, float2* const* p,
+           float4* const* q, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    if (K <= 0) return;
+    if (K <= 0) return 0;
     auto bind = [&](PdArgs& a) {
         a.u_in = u[iu]; a.v_in = v ? v[iu] : nullptr; a.p_in = p[ip]; a.q_in = q ? q[ip] : nullptr;
         a.u_out = u[1 - iu]; a.v_out = v ? v[1 - iu] : nullptr;
@@ -245,12 +246,29 @@ void run_pd(PdArgs base, const Sched& sc, int K, float* const* u, float2* const*
     bind(a);
     launch_pd(a, s);
     ip = 1 - ip;
-    if (ev0) (void)hipEventRecord(ev0, s);
-    for (int k = 1; k < K; ++k) {
+    // iterations 1 .. K-1: an odd one alone, then pairs in one pass each
+    int k = 1;
+    if ((K - 1) % 2) {
         a.mode = PD_FUSED;
         a.tau_scale = sc.s[k - 1];
         a.theta = sc.theta[k - 1];
         a.sigma_scale = 1.f / sc.s[k];
+        bind(a);
+        launch_pd(a, s);
+        iu = 1 - iu;
+        ip = 1 - ip;
+        ++k;
+    }
+    if (ev0) (void)hipEventRecord(ev0, s);
+    int pairs = 0;
+    for (; k + 1 <= K - 1; k += 2, ++pairs) {
+        a.mode = PD_FUSED2;
+        a.tau_scale = sc.s[k - 1];
+        a.theta = sc.theta[k - 1];
+        a.sigma_scale = 1.f / sc.s[k];
+        a.tau_scale2 = sc.s[k];
+        a.theta2 = sc.theta[k];
+        a.sigma_scale2 = 1.f / sc.s[k + 1];
         bind(a);
         launch_pd(a, s);
         iu = 1 - iu;
@@ -264,6 +282,7 @@ void run_pd(PdArgs base, const Sched& sc, int K, float* const* u, float2* const*
     bind(a);
     launch_pd(a, s);
     iu = 1 - iu;
+    return pairs;
 }
 
 }  // namespace
@@ -480,13 +499,14 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
             if (last) break;
             // A5: K primal-dual iterations (Eq. (11))
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (r->profile && l == 0 && params->iters >= 2) {
+            if (r->profile && l == 0 && params->iters >= 3) {
                 if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
                     return fail(VFS_E_DEVICE, "hipEventCreate");
                 r->events.emplace_back(e0, e1);
-                r->launches += params->iters - 1;
             }
-            run_pd(pa, sc, params->iters, r->u, tgv ? r->v : nullptr, r->p, tgv ? r->q : nullptr, iu, ip, s, e0, e1);
+            const int np = run_pd(pa, sc, params->iters, r->u, tgv ? r->v : nullptr, r->p, tgv ? r->q : nullptr, iu,
+                                  ip, s, e0, e1);
+            if (e0) r->launches += np;
         }
     }
     // A8: triangulation and outputs

@@ -6,35 +6,64 @@
 //     y^{k+1} = P(y^k + sigma K xbar^k),  x^{k+1} = prox(x^k - tau K^T y^{k+1}),
 //     xbar^{k+1} = x^{k+1} + theta (x^{k+1} - x^k),
 // with x = (u, v), y = (p, q), but the state in memory is stored one half
-// step apart, (x^{k-1}, y^k).  One launch (PD_FUSED) computes x^k on the
-// tile plus a one-pixel halo, forms xbar^k in registers and finishes with
-// y^{k+1}; xbar never touches memory.  A warp's K iterations are one
-// PD_DUAL_FIRST launch (y^1 from x^0 = xbar^0), K-1 PD_FUSED launches and one
-// PD_PRIMAL_LAST launch (x^K).  Every launch reads one copy of the state and
-// writes the other.
+// step apart, (x^{k-1}, y^k).  A PD_FUSED launch computes x^k on the tile plus
+// a one-pixel halo, forms xbar^k in registers and finishes with y^{k+1}; xbar
+// never touches memory.  A PD_FUSED2 launch does two such iterations in one
+// pass over memory: the second trails the first by two rows in the same
+// march, reading the first one's results from registers, so the state is read
+// and written once per two iterations.  A warp's K iterations are one
+// PD_DUAL_FIRST launch (y^1 from x^0 = xbar^0), (K-1) iterations of
+// PD_FUSED2 / PD_FUSED launches and one PD_PRIMAL_LAST launch (x^K).  Every
+// launch reads one copy of the state and writes the other.
 //
-// Work decomposition: one 64-lane wavefront owns 62 columns (lanes 1..62;
-// lanes 0 and 63 are the x-halo) and marches down BY rows plus a one-row
-// halo above and below, keeping the previous row's values in registers and
-// exchanging x-neighbours by lane shuffles.  A workgroup holds 4 wavefronts
-// stacked vertically.  Workgroups are renumbered so that the blocks the
-// dispatcher places on one XCD cover a contiguous band of tiles (their halo
-// re-reads then hit that XCD's L2).
+// Work decomposition: one 64-lane wavefront owns a strip of columns (62 for
+// the one-iteration modes: lanes 1..62, lanes 0 and 63 are the x-halo; 60 for
+// PD_FUSED2: lanes 2..61) and marches down 16 rows plus a halo above and
+// below, keeping the rows it still needs in registers and exchanging
+// x-neighbours by lane shifts.  A workgroup holds 4 wavefronts stacked
+// vertically.  Workgroups are renumbered so that the blocks the dispatcher
+// places on one XCD cover a contiguous band of tiles (their halo re-reads
+// then hit that XCD's L2).
 #include "vfs_internal.h"
 
 namespace vfs {
 
 namespace {
 
+#ifndef VFS_PD_BY
+#define VFS_PD_BY 16
+#endif
+#ifndef VFS_PD2_BY
+#define VFS_PD2_BY 16
+#endif
+#ifndef VFS_PD_DPP
+#define VFS_PD_DPP 1
+#endif
+
 constexpr int kLanes = 64;
-constexpr int kCols = kLanes - 2;   // interior columns per wavefront
-constexpr int kWaves = 4;           // wavefronts per workgroup
-constexpr int kBY = 16;             // rows per wavefront
+constexpr int kWaves = 4;            // wavefronts per workgroup
+constexpr int kCols = kLanes - 2;    // owned columns per wavefront, one-iteration modes
+constexpr int kBY = VFS_PD_BY;       // owned rows per wavefront, one-iteration modes
+constexpr int kCols2 = kLanes - 4;   // owned columns per wavefront, PD_FUSED2
+constexpr int kBY2 = VFS_PD2_BY;     // owned rows per wavefront, PD_FUSED2
 constexpr int kXcds = 8;
 
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+#if VFS_PD_DPP
+// whole-wavefront shifts by one lane (DPP wave_shr:1 / wave_shl:1); the lane
+// without a source receives 0 -- always a halo lane whose result is unused
+__device__ inline float from_left(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
+__device__ inline float from_right(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, false));
+}
+#else
 __device__ inline float from_left(float x) { return __shfl_up(x, 1, kLanes); }
 __device__ inline float from_right(float x) { return __shfl_down(x, 1, kLanes); }
+#endif
 
 struct Row {
     float u;
@@ -44,8 +73,7 @@ struct Row {
     unsigned f;
 };
 
-template <bool TGV, bool PRIMAL>
-__device__ inline Row load_row(const PdArgs& a, long long base, int x, int r, bool in_x)
+__device__ inline Row zero_row()
 {
     Row w;
     w.u = 0.f; w.rho = 0.f; w.f = 0u;
@@ -53,6 +81,13 @@ __device__ inline Row load_row(const PdArgs& a, long long base, int x, int r, bo
     w.p = make_float2(0.f, 0.f);
     w.q = make_float4(0.f, 0.f, 0.f, 0.f);
     w.t = make_float4(1.f, 0.f, 1.f, 0.f);
+    return w;
+}
+
+template <bool TGV, bool PRIMAL>
+__device__ inline Row load_row(const PdArgs& a, long long base, int x, int r, bool in_x)
+{
+    Row w = zero_row();
     if (in_x && r >= 0 && r < a.H) {
         const size_t o = base + (size_t)r * a.pitch + x;
         w.u = a.u_in[o];
@@ -68,6 +103,24 @@ __device__ inline Row load_row(const PdArgs& a, long long base, int x, int r, bo
     return w;
 }
 
+// What the primal step of row r reads from row r - 1 (the y-parts of the
+// masked divergences and of the column sums of the preconditioner).
+struct Above {
+    float b, cy, my, myq2, myq4;
+};
+
+__device__ inline Above above_of(float2 p, float4 q, float4 t, unsigned f)
+{
+    Above ab;
+    const float my = (f & F_MY) ? 1.f : 0.f;
+    ab.b = my * (t.y * p.x + t.z * p.y);
+    ab.cy = my * (fabsf(t.y) + fabsf(t.z));
+    ab.my = my;
+    ab.myq2 = my * q.y;
+    ab.myq4 = my * q.w;
+    return ab;
+}
+
 // Resolvent of the linearised data term, Eq. (13) (third case with the sign
 // that zeroes rho_bar = rho_c + u I_u).
 __device__ inline float resolvent(float uhat, float rho, float Iu, float tau, float lambda)
@@ -81,17 +134,100 @@ __device__ inline float resolvent(float uhat, float rho, float Iu, float tau, fl
     return uhat - rb / Iu;
 }
 
+// Primal step at one pixel: x^k from x^{k-1} = (u, v) and y^k = (p, q) at the
+// pixel, its left neighbour (lane shifts) and the row above (ab).  Called by
+// every lane of the wavefront (it shifts across lanes).  Returns (un, vn);
+// the pixel is left unchanged outside the mask.
+template <bool TGV>
+__device__ inline void primal_step(float u, float2 v, float2 p, float4 q, float4 t, float rho, unsigned f,
+                                   const Above& ab, float a0, float a1, float lambda, float ts, float& un,
+                                   float2& vn)
+{
+    const float mx = (f & F_MX) ? 1.f : 0.f;
+    const float my = (f & F_MY) ? 1.f : 0.f;
+    const float ax = mx * (t.x * p.x + t.y * p.y);
+    const float cx = mx * (fabsf(t.x) + fabsf(t.y));
+    const float ax_l = from_left(ax);
+    const float cx_l = from_left(cx);
+    const float b = my * (t.y * p.x + t.z * p.y);
+    const float divtp = ax - ax_l + b - ab.b;
+    const float cu = fabsf(t.x * mx + t.y * my) + fabsf(t.y * mx + t.z * my) + cx_l + ab.cy;
+    const float tau_u = (cu > 0.f ? frcp(a1 * cu) : frcp(a1)) * ts;
+    const float ur = resolvent(u + tau_u * a1 * divtp, rho, t.w, tau_u, lambda);
+    float2 vr = v;
+    if (TGV) {
+        const float mxq1 = mx * q.x, mxq3 = mx * q.z;
+        const float mxq1_l = from_left(mxq1), mxq3_l = from_left(mxq3), mx_l = from_left(mx);
+        const float d1 = mxq1 - mxq1_l + my * q.y - ab.myq2;
+        const float d2 = mxq3 - mxq3_l + my * q.w - ab.myq4;
+        const float tau_v = frcp(a1 + a0 * (mx + my + mx_l + ab.my)) * ts;
+        vr.x = v.x + tau_v * (a1 * p.x + a0 * d1);
+        vr.y = v.y + tau_v * (a1 * p.y + a0 * d2);
+    }
+    const bool msk = (f & F_MASK) != 0u;
+    un = msk ? ur : u;
+    vn = msk ? vr : v;
+}
+
+// Dual step at one pixel of row s: y^{k+1} from y^k = (p, q) and xbar^k at
+// the pixel (ub, vb), its right neighbour (ub_r, vb_r; shifted by the caller)
+// and the row below (ub_d, vb_d).  The duals stay as they are outside the mask.
+template <bool TGV>
+__device__ inline void dual_step(float2 p, float4 q, float4 t, unsigned f, float ub, float2 vb, float ub_r,
+                                 float2 vb_r, float ub_d, float2 vb_d, float a0, float a1, float ss, float2& pn,
+                                 float4& qn)
+{
+    pn = p;
+    qn = q;
+    if (!(f & F_MASK)) return;
+    const float pmx = (f & F_MX) ? 1.f : 0.f;
+    const float pmy = (f & F_MY) ? 1.f : 0.f;
+    const float gx = pmx * (ub_r - ub), gy = pmy * (ub_d - ub);
+    const float vrow = TGV ? a1 : 0.f;
+    const float s1 = a1 * (fabsf(t.x * pmx + t.y * pmy) + fabsf(t.x) * pmx + fabsf(t.y) * pmy) + vrow;
+    const float s2 = a1 * (fabsf(t.y * pmx + t.z * pmy) + fabsf(t.y) * pmx + fabsf(t.z) * pmy) + vrow;
+    const float smax = fmaxf(s1, s2);
+    const float sig = (smax > 0.f ? frcp(smax) : frcp(a1)) * ss;
+    float p1 = p.x + sig * a1 * (t.x * gx + t.y * gy - (TGV ? vb.x : 0.f));
+    float p2 = p.y + sig * a1 * (t.y * gx + t.z * gy - (TGV ? vb.y : 0.f));
+    const float n2 = p1 * p1 + p2 * p2;
+    if (n2 > 1.f) {
+        const float inv = __builtin_amdgcn_rsqf(n2);
+        p1 *= inv;
+        p2 *= inv;
+    }
+    pn = make_float2(p1, p2);
+    if (TGV) {
+        const float sq = ss / (2.f * a0);
+        float q1 = q.x + sq * a0 * pmx * (vb_r.x - vb.x);
+        float q2 = q.y + sq * a0 * pmy * (vb_d.x - vb.x);
+        float q3 = q.z + sq * a0 * pmx * (vb_r.y - vb.y);
+        float q4 = q.w + sq * a0 * pmy * (vb_d.y - vb.y);
+        const float m2 = q1 * q1 + q2 * q2 + q3 * q3 + q4 * q4;
+        if (m2 > 1.f) {
+            const float inv = __builtin_amdgcn_rsqf(m2);
+            q1 *= inv; q2 *= inv; q3 *= inv; q4 *= inv;
+        }
+        qn = make_float4(q1, q2, q3, q4);
+    }
+}
+
+// XCD-aware renumbering of the workgroup index.
+__device__ inline int logical_block()
+{
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int xcd = bid % kXcds, k = bid / kXcds, qn = nb / kXcds, rn = nb % kXcds;
+    return xcd < rn ? xcd * (qn + 1) + k : rn * (qn + 1) + (xcd - rn) * qn + k;
+}
+
+// One iteration (PD_FUSED) or its first / last half (PD_DUAL_FIRST, PD_PRIMAL_LAST).
 template <int MODE, bool TGV>
 __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
 {
     constexpr bool PRIMAL = MODE != PD_DUAL_FIRST;
     constexpr bool DUAL = MODE != PD_PRIMAL_LAST;
 
-    // XCD-aware renumbering of the workgroup
-    const int nb = gridDim.x, bid = blockIdx.x;
-    const int xcd = bid % kXcds, k = bid / kXcds, qn = nb / kXcds, rn = nb % kXcds;
-    const int logical = xcd < rn ? xcd * (qn + 1) + k : rn * (qn + 1) + (xcd - rn) * qn + k;
-
+    const int logical = logical_block();
     const int tiles_x = (a.W + kCols - 1) / kCols;
     const int tiles_y = (a.H + kBY * kWaves - 1) / (kBY * kWaves);
     const int tx = logical % tiles_x;
@@ -108,64 +244,28 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
     if (y0 >= a.H) return;
     const int y1 = min(y0 + kBY, a.H);          // owned rows [y0, y1)
     const long long base = (long long)pair * a.stride;
-
     const float a0 = a.alpha0, a1 = a.alpha1;
-    const float ts = a.tau_scale, ss = a.sigma_scale, th = a.theta;
-    const float sq = ss / (2.f * a0);           // sigma_q, scaled
 
-    // values of the previous row
+    // row r - 1 as the dual step needs it
     float2 p_prev = make_float2(0.f, 0.f);
     float4 q_prev = make_float4(0.f, 0.f, 0.f, 0.f), t_prev = make_float4(1.f, 0.f, 1.f, 0.f);
     unsigned f_prev = 0u;
     float ub_prev = 0.f;
     float2 vb_prev = make_float2(0.f, 0.f);
-    float b_prev = 0.f, cy_prev = 0.f, my_prev = 0.f, myq2_prev = 0.f, myq4_prev = 0.f;
-
+    Above ab = {0.f, 0.f, 0.f, 0.f, 0.f};
     if (PRIMAL) {
-        // row y0 - 1: only what the primal step of row y0 reads from above
         const Row w = load_row<TGV, false>(a, base, x, y0 - 1, in_x);
-        const float my = (w.f & F_MY) ? 1.f : 0.f;
-        b_prev = my * (w.t.y * w.p.x + w.t.z * w.p.y);
-        cy_prev = my * (fabsf(w.t.y) + fabsf(w.t.z));
-        my_prev = my;
-        myq2_prev = my * w.q.y;
-        myq4_prev = my * w.q.w;
+        ab = above_of(w.p, w.q, w.t, w.f);
     }
 
     const int r_end = DUAL ? y1 : y1 - 1;       // last row visited (row y1 is the look-ahead)
     for (int r = y0; r <= r_end; ++r) {
         const Row c = load_row<TGV, PRIMAL>(a, base, x, r, in_x);
-        const float mx = (c.f & F_MX) ? 1.f : 0.f;
-        const float my = (c.f & F_MY) ? 1.f : 0.f;
-        const bool msk = (c.f & F_MASK) != 0u;
-
-        // ---- primal step at row r: x^k from x^{k-1} and y^k
+        // primal step at row r: x^k from x^{k-1} and y^k
         float un = c.u;
         float2 vn = c.v;
-        const float b = my * (c.t.y * c.p.x + c.t.z * c.p.y);
-        const float cy = my * (fabsf(c.t.y) + fabsf(c.t.z));
-        const float myq2 = my * c.q.y, myq4 = my * c.q.w;
         if (PRIMAL) {
-            const float ax = mx * (c.t.x * c.p.x + c.t.y * c.p.y);
-            const float cx = mx * (fabsf(c.t.x) + fabsf(c.t.y));
-            const float ax_l = from_left(ax);
-            const float cx_l = from_left(cx);
-            const float divtp = ax - ax_l + b - b_prev;
-            const float cu = fabsf(c.t.x * mx + c.t.y * my) + fabsf(c.t.y * mx + c.t.z * my) + cx_l + cy_prev;
-            const float tau_u = (cu > 0.f ? frcp(a1 * cu) : frcp(a1)) * ts;
-            const float uh = c.u + tau_u * a1 * divtp;
-            const float ur = resolvent(uh, c.rho, c.t.w, tau_u, a.lambda);
-            float2 vr = c.v;
-            if (TGV) {
-                const float mxq1 = mx * c.q.x, mxq3 = mx * c.q.z;
-                const float mxq1_l = from_left(mxq1), mxq3_l = from_left(mxq3), mx_l = from_left(mx);
-                const float d1 = mxq1 - mxq1_l + myq2 - myq2_prev;
-                const float d2 = mxq3 - mxq3_l + myq4 - myq4_prev;
-                const float tau_v = frcp(a1 + a0 * (mx + my + mx_l + my_prev)) * ts;
-                vr.x = c.v.x + tau_v * (a1 * c.p.x + a0 * d1);
-                vr.y = c.v.y + tau_v * (a1 * c.p.y + a0 * d2);
-            }
-            if (msk) { un = ur; vn = vr; }
+            primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab, a0, a1, a.lambda, a.tau_scale, un, vn);
             if (owner && r < y1) {
                 const size_t o = base + (size_t)r * a.pitch + x;
                 a.u_out[o] = un;
@@ -173,66 +273,162 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
             }
         }
         // over-relaxation (xbar stays in registers)
-        const float ub = un + th * (un - c.u);
-        const float2 vb = make_float2(vn.x + th * (vn.x - c.v.x), vn.y + th * (vn.y - c.v.y));
-
-        // ---- dual step at row r - 1: y^{k+1} from y^k and xbar^k
+        const float ub = un + a.theta * (un - c.u);
+        const float2 vb = make_float2(vn.x + a.theta * (vn.x - c.v.x), vn.y + a.theta * (vn.y - c.v.y));
+        // dual step at row r - 1: y^{k+1} from y^k and xbar^k
         if (DUAL) {
             const float ub_r = from_right(ub_prev);
-            const float vb1_r = from_right(vb_prev.x), vb2_r = from_right(vb_prev.y);
-            if (r > y0 && owner && (f_prev & F_MASK)) {
-                const float pmx = (f_prev & F_MX) ? 1.f : 0.f;
-                const float pmy = (f_prev & F_MY) ? 1.f : 0.f;
-                const float4 t = t_prev;
-                const float gx = pmx * (ub_r - ub_prev), gy = pmy * (ub - ub_prev);
-                const float s1 = a1 * (fabsf(t.x * pmx + t.y * pmy) + fabsf(t.x) * pmx + fabsf(t.y) * pmy) +
-                                 (TGV ? a1 : 0.f);
-                const float s2 = a1 * (fabsf(t.y * pmx + t.z * pmy) + fabsf(t.y) * pmx + fabsf(t.z) * pmy) +
-                                 (TGV ? a1 : 0.f);
-                const float smax = fmaxf(s1, s2);
-                const float sig = (smax > 0.f ? frcp(smax) : frcp(a1)) * ss;
-                float p1 = p_prev.x + sig * a1 * (t.x * gx + t.y * gy - (TGV ? vb_prev.x : 0.f));
-                float p2 = p_prev.y + sig * a1 * (t.y * gx + t.z * gy - (TGV ? vb_prev.y : 0.f));
-                const float n2 = p1 * p1 + p2 * p2;
-                if (n2 > 1.f) {
-                    const float inv = __builtin_amdgcn_rsqf(n2);
-                    p1 *= inv;
-                    p2 *= inv;
-                }
+            const float2 vb_r = make_float2(from_right(vb_prev.x), from_right(vb_prev.y));
+            if (r > y0 && owner) {
+                float2 pn;
+                float4 qn;
+                dual_step<TGV>(p_prev, q_prev, t_prev, f_prev, ub_prev, vb_prev, ub_r, vb_r, ub, vb, a0, a1,
+                               a.sigma_scale, pn, qn);
                 const size_t o = base + (size_t)(r - 1) * a.pitch + x;
-                a.p_out[o] = make_float2(p1, p2);
-                if (TGV) {
-                    float q1 = q_prev.x + sq * a0 * pmx * (vb1_r - vb_prev.x);
-                    float q2 = q_prev.y + sq * a0 * pmy * (vb.x - vb_prev.x);
-                    float q3 = q_prev.z + sq * a0 * pmx * (vb2_r - vb_prev.y);
-                    float q4 = q_prev.w + sq * a0 * pmy * (vb.y - vb_prev.y);
-                    const float m2 = q1 * q1 + q2 * q2 + q3 * q3 + q4 * q4;
-                    if (m2 > 1.f) {
-                        const float inv = __builtin_amdgcn_rsqf(m2);
-                        q1 *= inv; q2 *= inv; q3 *= inv; q4 *= inv;
-                    }
-                    a.q_out[o] = make_float4(q1, q2, q3, q4);
-                }
-            } else if (r > y0 && owner) {
-                // outside the mask the duals stay as they are (zero)
-                const size_t o = base + (size_t)(r - 1) * a.pitch + x;
-                a.p_out[o] = p_prev;
-                if (TGV) a.q_out[o] = q_prev;
+                a.p_out[o] = pn;
+                if (TGV) a.q_out[o] = qn;
             }
         }
-
-        // ---- slide the window
+        // slide the window
         p_prev = c.p;
         q_prev = c.q;
         t_prev = c.t;
         f_prev = c.f;
         ub_prev = ub;
         vb_prev = vb;
-        b_prev = b;
-        cy_prev = cy;
-        my_prev = my;
-        myq2_prev = myq2;
-        myq4_prev = myq4;
+        ab = above_of(c.p, c.q, c.t, c.f);
+    }
+}
+
+// Two iterations per pass (PD_FUSED2): (x^{k-1}, y^k) -> (x^{k+1}, y^{k+2}).
+// At step r of the march: A = primal of iteration 1 at row r, B = dual of
+// iteration 1 at row r-1, C = primal of iteration 2 at row r-2 (reads A's
+// x^k and B's y^{k+1} from registers), D = dual of iteration 2 at row r-3.
+// The wavefront owns rows [y0, y1) and marches r = y0-1 .. y1+2 (row y0-2 is
+// read for A's first "above").  Column validity shrinks by one lane per
+// stage away from the wavefront's edges: A is exact on lanes 1..63, B on
+// 1..62, C on 2..62, D on 2..61 -- the owned lanes.
+template <bool TGV>
+__global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
+{
+    const int logical = logical_block();
+    const int tiles_x = (a.W + kCols2 - 1) / kCols2;
+    const int tiles_y = (a.H + kBY2 * kWaves - 1) / (kBY2 * kWaves);
+    const int tx = logical % tiles_x;
+    const int ty = (logical / tiles_x) % tiles_y;
+    const int pair = logical / (tiles_x * tiles_y);
+    if (pair >= a.n) return;
+
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int wave = threadIdx.x / kLanes;
+    const int x = tx * kCols2 - 2 + lane;
+    const bool in_x = x >= 0 && x < a.W;
+    const bool owner = lane >= 2 && lane <= kCols2 + 1 && in_x;
+    const int y0 = (ty * kWaves + wave) * kBY2;
+    if (y0 >= a.H) return;
+    const int y1 = min(y0 + kBY2, a.H);
+    const long long base = (long long)pair * a.stride;
+    const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
+
+    // iteration 1: "above" of row r-1, and row r-1 as B needs it
+    Above ab1;
+    {
+        const Row w = load_row<TGV, false>(a, base, x, y0 - 2, in_x);
+        ab1 = above_of(w.p, w.q, w.t, w.f);
+    }
+    float2 p_m1 = make_float2(0.f, 0.f);
+    float4 q_m1 = make_float4(0.f, 0.f, 0.f, 0.f), t_m1 = make_float4(1.f, 0.f, 1.f, 0.f);
+    unsigned f_m1 = 0u;
+    float rho_m1 = 0.f, ub1_m1 = 0.f;
+    float2 vb1_m1 = make_float2(0.f, 0.f);
+    // x^k of rows r-1, r-2 (A's results), constants of rows r-2, r-3
+    float un1_m1 = 0.f, un1_m2 = 0.f;
+    float2 vn1_m1 = make_float2(0.f, 0.f), vn1_m2 = make_float2(0.f, 0.f);
+    float4 t_m2 = make_float4(1.f, 0.f, 1.f, 0.f), t_m3 = make_float4(1.f, 0.f, 1.f, 0.f);
+    float rho_m2 = 0.f;
+    unsigned f_m2 = 0u, f_m3 = 0u;
+    // y^{k+1} of rows r-2, r-3 (B's results); "above" of iteration 2; xbar^{k+1} of row r-3
+    float2 p1_m2 = make_float2(0.f, 0.f), p1_m3 = make_float2(0.f, 0.f);
+    float4 q1_m2 = make_float4(0.f, 0.f, 0.f, 0.f), q1_m3 = make_float4(0.f, 0.f, 0.f, 0.f);
+    Above ab2 = {0.f, 0.f, 0.f, 0.f, 0.f};
+    float ub2_m3 = 0.f;
+    float2 vb2_m3 = make_float2(0.f, 0.f);
+
+    for (int r = y0 - 1; r <= y1 + 2; ++r) {
+        // A: iteration-1 primal at row r
+        Row c = zero_row();
+        float un1 = 0.f, ub1 = 0.f;
+        float2 vn1 = make_float2(0.f, 0.f), vb1 = make_float2(0.f, 0.f);
+        if (r <= y1 + 1) {
+            c = load_row<TGV, true>(a, base, x, r, in_x);
+            primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, a.tau_scale, un1, vn1);
+            ub1 = un1 + a.theta * (un1 - c.u);
+            vb1 = make_float2(vn1.x + a.theta * (vn1.x - c.v.x), vn1.y + a.theta * (vn1.y - c.v.y));
+        }
+        // B: iteration-1 dual at row r-1 -> y^{k+1}(r-1)
+        float2 p1 = make_float2(0.f, 0.f);
+        float4 q1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r >= y0 && r <= y1 + 1) {
+            const float ub_r = from_right(ub1_m1);
+            const float2 vb_r = make_float2(from_right(vb1_m1.x), from_right(vb1_m1.y));
+            dual_step<TGV>(p_m1, q_m1, t_m1, f_m1, ub1_m1, vb1_m1, ub_r, vb_r, ub1, vb1, a0, a1, a.sigma_scale,
+                           p1, q1);
+        }
+        // C: iteration-2 primal at row r-2 -> x^{k+1}(r-2)
+        float ub2 = 0.f;
+        float2 vb2 = make_float2(0.f, 0.f);
+        if (r >= y0 + 2) {
+            float un2;
+            float2 vn2;
+            primal_step<TGV>(un1_m2, vn1_m2, p1_m2, q1_m2, t_m2, rho_m2, f_m2, ab2, a0, a1, lam, a.tau_scale2,
+                             un2, vn2);
+            ub2 = un2 + a.theta2 * (un2 - un1_m2);
+            vb2 = make_float2(vn2.x + a.theta2 * (vn2.x - vn1_m2.x), vn2.y + a.theta2 * (vn2.y - vn1_m2.y));
+            if (owner && r - 2 < y1) {
+                const size_t o = base + (size_t)(r - 2) * a.pitch + x;
+                a.u_out[o] = un2;
+                if (TGV) a.v_out[o] = vn2;
+            }
+        }
+        // D: iteration-2 dual at row r-3 -> y^{k+2}(r-3)
+        if (r >= y0 + 3) {
+            const float ub_r = from_right(ub2_m3);
+            const float2 vb_r = make_float2(from_right(vb2_m3.x), from_right(vb2_m3.y));
+            float2 pn;
+            float4 qn;
+            dual_step<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1, a.sigma_scale2,
+                           pn, qn);
+            if (owner) {
+                const size_t o = base + (size_t)(r - 3) * a.pitch + x;
+                a.p_out[o] = pn;
+                if (TGV) a.q_out[o] = qn;
+            }
+        }
+        // slide the windows (deepest first)
+        ab2 = above_of(p1_m2, q1_m2, t_m2, f_m2);      // row r-2, for C at row r-1
+        t_m3 = t_m2;
+        f_m3 = f_m2;
+        p1_m3 = p1_m2;
+        q1_m3 = q1_m2;
+        ub2_m3 = ub2;
+        vb2_m3 = vb2;
+        t_m2 = t_m1;
+        f_m2 = f_m1;
+        rho_m2 = rho_m1;
+        p1_m2 = p1;
+        q1_m2 = q1;
+        un1_m2 = un1_m1;
+        vn1_m2 = vn1_m1;
+        un1_m1 = un1;
+        vn1_m1 = vn1;
+        p_m1 = c.p;
+        q_m1 = c.q;
+        t_m1 = c.t;
+        f_m1 = c.f;
+        rho_m1 = c.rho;
+        ub1_m1 = ub1;
+        vb1_m1 = vb1;
+        ab1 = above_of(c.p, c.q, c.t, c.f);
     }
 }
 
@@ -245,6 +441,15 @@ void launch_mode(const PdArgs& a, hipStream_t s)
     hipLaunchKernelGGL((pd_kernel<MODE, TGV>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
 }
 
+template <bool TGV>
+void launch_fused2(const PdArgs& a, hipStream_t s)
+{
+    const int tiles_x = (a.W + kCols2 - 1) / kCols2;
+    const int tiles_y = (a.H + kBY2 * kWaves - 1) / (kBY2 * kWaves);
+    const int nb = tiles_x * tiles_y * a.n;
+    hipLaunchKernelGGL((pd2_kernel<TGV>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
+}
+
 }  // namespace
 
 void launch_pd(const PdArgs& a, hipStream_t s)
@@ -252,10 +457,12 @@ void launch_pd(const PdArgs& a, hipStream_t s)
     if (a.tgv) {
         if (a.mode == PD_DUAL_FIRST) launch_mode<PD_DUAL_FIRST, true>(a, s);
         else if (a.mode == PD_FUSED) launch_mode<PD_FUSED, true>(a, s);
+        else if (a.mode == PD_FUSED2) launch_fused2<true>(a, s);
         else launch_mode<PD_PRIMAL_LAST, true>(a, s);
     } else {
         if (a.mode == PD_DUAL_FIRST) launch_mode<PD_DUAL_FIRST, false>(a, s);
         else if (a.mode == PD_FUSED) launch_mode<PD_FUSED, false>(a, s);
+        else if (a.mode == PD_FUSED2) launch_fused2<false>(a, s);
         else launch_mode<PD_PRIMAL_LAST, false>(a, s);
     }
 }

