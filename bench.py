@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 # textbook state (with ubar, vbar in memory) would move 117 B per
 # pixel-iteration.
 BYTES_PER_PIX_LAUNCH = 93
+# The same kernel with p, q and the tensor pack stored as 16-bit values:
+# reads u 4, v 8, p 4, q 8, tensor pack 8, rho_c 4, flags 1; writes u 4, v 8, p 4, q 8.
+BYTES_PER_PIX_LAUNCH_16 = 61
 ITERS_PER_LAUNCH = 2
 TEXTBOOK_BYTES_PER_PIX_ITER = 117
 HBM_PEAK_GBS = 8000.0
@@ -44,6 +47,7 @@ def main():
     ap.add_argument("--config", default="c5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage measurement")
     ap.add_argument("--input-cache", default=None,
                     help="npz file to reuse rendered inputs across runs (written if missing)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -124,6 +128,28 @@ def main():
                 "effective_textbook_GBs": round(effective, 1),
                 "level0_Mpix_iter_s": round(ITERS_PER_LAUNCH * W * H * n / avg_launch_s / 1e6, 1)}
 
+    fp16 = None
+    if not args.no_fp16:
+        p16 = dict(params, storage=1)
+        outs16 = vfs.solve_batch(R, I0s, I1s, p16, betas=betas, etas=etas)
+        torch.cuda.synchronize()
+        vfs.profile_enable(R, True)
+        vfs.profile_read(R, reset=True)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            outs16 = vfs.solve_batch(R, I0s, I1s, p16, betas=betas, etas=etas, out=outs16)
+        torch.cuda.synchronize()
+        dt16 = time.perf_counter() - t0
+        ms16, n16 = vfs.profile_read(R, reset=True)
+        vfs.profile_enable(R, False)
+        a16 = (ms16 / n16) / 1e3 if n16 else float("nan")
+        du = torch.stack([(o16["u"] - o["u"]).abs().mean() for o16, o in zip(outs16, outs)]).mean().item()
+        fp16 = {"value": round(pix_iter / (dt16 / args.steps) / 1e6, 1), "ms_per_step": round(1e3 * dt16 / args.steps, 2),
+                "avg_launch_us": round(a16 * 1e6, 2),
+                "achieved_GBs": round(BYTES_PER_PIX_LAUNCH_16 * W * H * n / a16 / 1e9, 1),
+                "mean_abs_u_diff_vs_fp32_px": round(du, 5)}
+        log(f"bench: fp16 storage {args.steps} steps in {dt16:.3f} s")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, rig, pairs[0], tens[0], params, args.cpu_seconds)
@@ -139,6 +165,7 @@ def main():
                    "iters": cfg["iters"], "pix_iter_per_step": pix_iter},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "fp16_storage": fp16,
     }
     print(json.dumps(line), flush=True)
 

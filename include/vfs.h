@@ -50,7 +50,10 @@ typedef enum {
 
 typedef enum { VFS_PINHOLE = 0, VFS_EQUIDISTANT = 1, VFS_KANNALA_BRANDT = 2 } vfs_model;
 typedef enum { VFS_TGV = 0, VFS_TV = 1 } vfs_reg;
-typedef enum { VFS_F32 = 0 } vfs_storage;
+/* Storage of the dual variables and of the tensor pack (T^(1/2) of Eq. (12)
+ * and I_u): 32-bit float, IEEE half or bfloat16; every update is computed in
+ * FP32 and u, v, rho_c stay FP32 (rho_c is formed from I_u as stored). */
+typedef enum { VFS_F32 = 0, VFS_F16 = 1, VFS_BF16 = 2 } vfs_storage;
 
 /* Camera: r_d(theta) = theta + k1 theta^3 + k2 theta^5 + k3 theta^7 +
  * k4 theta^9 (Kannala-Brandt; equidistant is k = 0; pinhole r_d = tan theta),
@@ -140,13 +143,14 @@ vfs_status vfs_solve(vfs_rig* rig, const float* I0, const float* I1, size_t pitc
                      const vfs_params* params, void* hip_stream);
 
 /* ---- Steps of the method on caller buffers (device), for step-by-step use
- * and testing.  Layout: row-major with a common row pitch of `pitch`
+ * and testing; they use FP32 storage whatever params->storage says.
+ * Layout: row-major with a common row pitch of `pitch`
  * ELEMENTS (not bytes) for every plane; vector planes interleave their
  * components (float2 (x, y) per pixel for w, gamma, v, p; float4 for q and
  * for the tensor pack (t11, t12, t22, I_u)).  flags as in vfs_rig_field. */
 
 /* Eq. (12): tensor from the level image J0 and the flags (mask bit), written
- * to tpack.xyz (tpack.w untouched).  Central differences, one-sided where a
+ * to tpack.xyz (tpack.w set to 0).  Central differences, one-sided where a
  * neighbour leaves the image or the mask; T = I where the gradient is below
  * 1e-12 or the pixel is masked out. */
 vfs_status vfs_step_tensor(int width, int height, size_t pitch, const float* J0, const uint8_t* flags,

@@ -108,9 +108,9 @@ struct vfs_rig {
     float* uw = nullptr;
     float2* w[2] = {};
     float2* v[2] = {};
-    float2* p[2] = {};
-    float4* q[2] = {};
-    float4* tpack = nullptr;
+    void* p[2] = {};            // float2 / 2 x 16-bit per pixel, by storage
+    void* q[2] = {};            // float4 / 4 x 16-bit
+    void* tpack = nullptr;      // float4 / 4 x 16-bit
     float* rho = nullptr;
     float2* gw = nullptr;
 
@@ -182,11 +182,11 @@ vfs_status ensure_workspace(vfs_rig* r, int n)
     r->w[1] = reinterpret_cast<float2*>(take(2 * r->n0));
     r->v[0] = reinterpret_cast<float2*>(take(2 * r->n0));
     r->v[1] = reinterpret_cast<float2*>(take(2 * r->n0));
-    r->p[0] = reinterpret_cast<float2*>(take(2 * r->n0));
-    r->p[1] = reinterpret_cast<float2*>(take(2 * r->n0));
-    r->q[0] = reinterpret_cast<float4*>(take(4 * r->n0));
-    r->q[1] = reinterpret_cast<float4*>(take(4 * r->n0));
-    r->tpack = reinterpret_cast<float4*>(take(4 * r->n0));
+    r->p[0] = take(2 * r->n0);
+    r->p[1] = take(2 * r->n0);
+    r->q[0] = take(4 * r->n0);
+    r->q[1] = take(4 * r->n0);
+    r->tpack = take(4 * r->n0);
     r->rho = take(r->n0);
     r->gw = reinterpret_cast<float2*>(take(2 * r->n0));
     return VFS_OK;
@@ -219,7 +219,8 @@ vfs_status check_params(const vfs_params* p)
     if (p->levels < 1 || p->levels > kMaxLevels) return fail(VFS_E_INVALID, "levels must be in [1, %d]", kMaxLevels);
     if (p->warps < 0 || p->iters < 0) return fail(VFS_E_INVALID, "warps and iters must be >= 0");
     if (p->reg != VFS_TGV && p->reg != VFS_TV) return fail(VFS_E_INVALID, "bad regulariser");
-    if (p->storage != VFS_F32) return fail(VFS_E_INVALID, "unsupported storage");
+    if (p->storage != VFS_F32 && p->storage != VFS_F16 && p->storage != VFS_BF16)
+        return fail(VFS_E_INVALID, "unsupported storage");
     if (!(p->alpha0 > 0.0) || !(p->alpha1 > 0.0) || !(p->lambda >= 0.0) || !(p->du_max > 0.0) ||
         !(p->theta_gamma >= 0.0) || !(p->beta >= 0.0) || !(p->eta > 0.0))
         return fail(VFS_E_INVALID, "bad solver constants");
@@ -229,8 +230,8 @@ vfs_status check_params(const vfs_params* p)
 // K primal-dual iterations from a warp start on the state index pair (iu, ip);
 // the indices are updated to those holding the result.  Returns the number of
 // two-iteration launches, which ev0 / ev1 (if given) bracket.
-int run_pd(PdArgs base, const Sched& sc, int K, float* const* u, float2* const* v, float2* const* p,
-           float4* const* q, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+int run_pd(PdArgs base, const Sched& sc, int K, float* const* u, float2* const* v, void* const* p,
+           void* const* q, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (K <= 0) return 0;
     auto bind = [&](PdArgs& a) {
@@ -462,16 +463,17 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
     for (int l = L - 1; l >= 0; --l) {
         const Level& lv = r->lv[l];
         // A3: tensor of the level (Eq. (12))
-        launch_tensor(n, lv.W, lv.H, j0[l], j0pitch[l], 0, r->flags[l], lv.pitch, bet, et, r->tpack, lv.pitch, N0, s);
+        launch_tensor(n, lv.W, lv.H, j0[l], j0pitch[l], 0, r->flags[l], lv.pitch, bet, et, r->tpack, lv.pitch, N0,
+                      params->storage, s);
         // A7: state of the level: zero at the coarsest, else transferred from level l+1
         if (l == L - 1) {
             launch_zero_state(n, lv.W, lv.H, lv.pitch, N0, r->u[iu], r->w[iw], tgv ? r->v[iu] : nullptr, r->p[ip],
-                              tgv ? r->q[ip] : nullptr, s);
+                              tgv ? r->q[ip] : nullptr, params->storage, s);
         } else {
             const Level& lc = r->lv[l + 1];
             launch_upsample(n, lc.W, lc.H, lc.pitch, N0, r->flags[l + 1], lc.pitch, r->u[iu], r->w[iw], lv.pitch, N0,
                             r->u[1 - iu], r->w[1 - iw], tgv ? r->v[1 - iu] : nullptr, r->p[ip],
-                            tgv ? r->q[ip] : nullptr, s);
+                            tgv ? r->q[ip] : nullptr, params->storage, s);
             iu = 1 - iu;
             iw = 1 - iw;
         }
@@ -488,6 +490,7 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
         pa.alpha1 = float(params->alpha1);
         pa.lambda = float(params->lambda);
         pa.tgv = tgv ? 1 : 0;
+        pa.storage = params->storage;
         const float* J1l = r->J1 + r->off1[l];
         for (int wv = 0; wv <= params->warps; ++wv) {
             // A4 (+A6 of the previous warp): clip, accumulate, linearise
@@ -495,7 +498,7 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
             if (last && wv == 0) break;
             launch_linearise(n, lv.W, lv.H, lv.pitch, N0, j0[l], j0pitch[l], 0, J1l, (long long)r->sj1, r->gamma[l],
                              r->flags[l], r->u[iu], r->uw, r->w[iw], r->gw, r->tpack, r->rho, wv > 0 ? 1 : 0,
-                             last ? 1 : 0, float(params->du_max), s);
+                             last ? 1 : 0, float(params->du_max), params->storage, s);
             if (last) break;
             // A5: K primal-dual iterations (Eq. (11))
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -533,8 +536,8 @@ vfs_status vfs_step_tensor(int W, int H, size_t pitch, const float* J0, const ui
         return fail(VFS_E_INVALID, "bad argument");
     const float* j[1] = {J0};
     const float b = float(beta), e = float(eta);
-    launch_tensor(1, W, H, j, int(pitch), 0, flags, int(pitch), &b, &e, reinterpret_cast<float4*>(tpack), int(pitch),
-                  0, static_cast<hipStream_t>(hip_stream));
+    launch_tensor(1, W, H, j, int(pitch), 0, flags, int(pitch), &b, &e, tpack, int(pitch), 0, ST_F32,
+                  static_cast<hipStream_t>(hip_stream));
     HIP_OK(hipGetLastError());
     return VFS_OK;
 }
@@ -549,9 +552,8 @@ vfs_status vfs_step_linearise(int W, int H, size_t pitch, const float* J0, const
         return fail(VFS_E_INVALID, "bad argument");
     const float* j[1] = {J0};
     launch_linearise(1, W, H, int(pitch), 0, j, int(pitch), 0, J1, 0, reinterpret_cast<const float2*>(gamma), flags, u,
-                     u_w, reinterpret_cast<float2*>(w), reinterpret_cast<float2*>(gamma_w),
-                     reinterpret_cast<float4*>(tpack), rho, clip ? 1 : 0, clip_only ? 1 : 0, float(du_max),
-                     static_cast<hipStream_t>(hip_stream));
+                     u_w, reinterpret_cast<float2*>(w), reinterpret_cast<float2*>(gamma_w), tpack, rho, clip ? 1 : 0,
+                     clip_only ? 1 : 0, float(du_max), ST_F32, static_cast<hipStream_t>(hip_stream));
     HIP_OK(hipGetLastError());
     return VFS_OK;
 }
@@ -574,7 +576,8 @@ vfs_status vfs_step_pd(int W, int H, size_t pitch, const float* tpack, const flo
     const Sched sc = schedule(pp);
     PdArgs a{};
     a.W = W; a.H = H; a.pitch = int(pitch); a.stride = 0; a.n = 1;
-    a.tpack = reinterpret_cast<const float4*>(tpack);
+    a.tpack = tpack;
+    a.storage = ST_F32;
     a.rho = rho;
     a.flags = flags;
     a.alpha0 = float(params->alpha0);
@@ -583,8 +586,8 @@ vfs_status vfs_step_pd(int W, int H, size_t pitch, const float* tpack, const flo
     a.tgv = tgv ? 1 : 0;
     float* U[2] = {u, su};
     float2* V[2] = {reinterpret_cast<float2*>(v), reinterpret_cast<float2*>(sv)};
-    float2* P[2] = {reinterpret_cast<float2*>(p), reinterpret_cast<float2*>(sp)};
-    float4* Q[2] = {reinterpret_cast<float4*>(q), reinterpret_cast<float4*>(sq)};
+    void* P[2] = {p, sp};
+    void* Q[2] = {q, sq};
     int iu = 0, ip = 0;
     run_pd(a, sc, iters, U, tgv ? V : nullptr, P, tgv ? Q : nullptr, iu, ip, s, nullptr, nullptr);
     const size_t plane = pitch * size_t(H);
@@ -608,7 +611,7 @@ vfs_status vfs_step_upsample(int Wc, int Hc, size_t pitch_c, const uint8_t* flag
         !w_f)
         return fail(VFS_E_INVALID, "bad argument");
     launch_upsample(1, Wc, Hc, int(pitch_c), 0, flags_c, int(pitch_c), u_c, reinterpret_cast<const float2*>(w_c),
-                    int(pitch_f), 0, u_f, reinterpret_cast<float2*>(w_f), nullptr, nullptr, nullptr,
+                    int(pitch_f), 0, u_f, reinterpret_cast<float2*>(w_f), nullptr, nullptr, nullptr, ST_F32,
                     static_cast<hipStream_t>(hip_stream));
     HIP_OK(hipGetLastError());
     return VFS_OK;

@@ -94,8 +94,9 @@ __device__ inline bool in_mask(const uint8_t* flags, int fpitch, int W, int H, i
 
 struct Params2 { float beta[kMaxBatch]; float eta[kMaxBatch]; };
 
+template <int S>
 __global__ void tensor_kernel(int W, int H, FinePtrs J0, int jpitch, long long jstride, const uint8_t* flags,
-                              int fpitch, Params2 be, float4* tpack, int tpitch, long long tstride)
+                              int fpitch, Params2 be, void* tpack, int tpitch, long long tstride)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y, b = blockIdx.z;
@@ -121,13 +122,14 @@ __global__ void tensor_kernel(int W, int H, FinePtrs J0, int jpitch, long long j
             t = make_float4(e * nx * nx + ny * ny, (e - 1.f) * nx * ny, e * ny * ny + nx * nx, 0.f);
         }
     }
-    tpack[b * tstride + (size_t)i * tpitch + j] = t;
+    st4<S>(tpack, b * tstride + (size_t)i * tpitch + j, t);
 }
 
+template <int S>
 __global__ void linearise_kernel(int W, int H, int pitch, long long stride, FinePtrs J0, int j0pitch,
                                  long long j0stride, const float* J1, long long j1stride, const float2* gamma,
                                  const uint8_t* flags, float* u, float* u_w, float2* w, float2* gamma_w,
-                                 float4* tpack, float* rho, int clip, int clip_only, float du_max)
+                                 void* tpack, float* rho, int clip, int clip_only, float du_max)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y, b = blockIdx.z;
@@ -159,16 +161,24 @@ __global__ void linearise_kernel(int W, int H, int pitch, long long stride, Fine
         const float i1 = bilinear(J1b, pitch, W, H, j, i, ww.x, ww.y);
         const float i1s = bilinear(J1b, pitch, W, H, j, i, ww.x + g.x, ww.y + g.y);
         const float* J0b = J0.p[b] + (j0stride ? b * j0stride : 0);
-        Iu = i1s - i1;
+        // rho_c is formed from I_u as stored, so that rho_c + u I_u is exact at u = u_w
+        Iu = as_stored<S>(i1s - i1);
         rc = i1 - J0b[(size_t)i * j0pitch + j] - uu * Iu;
     }
-    tpack[o].w = Iu;
+    if constexpr (S == ST_F32) {
+        static_cast<float4*>(tpack)[o].w = Iu;
+    } else {
+        float4 t = ld4<S>(tpack, o);
+        t.w = Iu;
+        st4<S>(tpack, o, t);
+    }
     rho[o] = rc;
 }
 
+template <int S>
 __global__ void upsample_kernel(int Wc, int Hc, int cpitch, long long cstride, const uint8_t* flags_c, int fcpitch,
                                 const float* u_c, const float2* w_c, int fpitch, long long fstride, float* u_f,
-                                float2* w_f, float2* v_f, float2* p_f, float4* q_f)
+                                float2* w_f, float2* v_f, void* p_f, void* q_f)
 {
     const int Wf = 2 * Wc;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,12 +211,13 @@ __global__ void upsample_kernel(int Wc, int Hc, int cpitch, long long cstride, c
         w_f[fo] = make_float2(0.f, 0.f);
     }
     if (v_f) v_f[fo] = make_float2(0.f, 0.f);
-    if (p_f) p_f[fo] = make_float2(0.f, 0.f);
-    if (q_f) q_f[fo] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p_f) st2<S>(p_f, fo, make_float2(0.f, 0.f));
+    if (q_f) st4<S>(q_f, fo, make_float4(0.f, 0.f, 0.f, 0.f));
 }
 
-__global__ void zero_state_kernel(int W, int pitch, long long stride, float* u, float2* w, float2* v, float2* p,
-                                  float4* q)
+template <int S>
+__global__ void zero_state_kernel(int W, int pitch, long long stride, float* u, float2* w, float2* v, void* p,
+                                  void* q)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y, b = blockIdx.z;
@@ -215,8 +226,8 @@ __global__ void zero_state_kernel(int W, int pitch, long long stride, float* u, 
     u[o] = 0.f;
     w[o] = make_float2(0.f, 0.f);
     if (v) v[o] = make_float2(0.f, 0.f);
-    p[o] = make_float2(0.f, 0.f);
-    if (q) q[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+    st2<S>(p, o, make_float2(0.f, 0.f));
+    if (q) st4<S>(q, o, make_float4(0.f, 0.f, 0.f, 0.f));
 }
 
 struct OutPtrs {
@@ -282,9 +293,16 @@ void launch_downsample(int n, int Wc, int Hc, const float* const* fine, int fpit
                        cpitch, cstride);
 }
 
+#define VFS_BY_STORAGE(storage, call)                   \
+    do {                                                \
+        if ((storage) == ST_F16) { constexpr int S = ST_F16; call; }         \
+        else if ((storage) == ST_BF16) { constexpr int S = ST_BF16; call; }  \
+        else { constexpr int S = ST_F32; call; }                             \
+    } while (0)
+
 void launch_tensor(int n, int W, int H, const float* const* J0, int jpitch, long long jstride, const uint8_t* flags,
-                   int fpitch, const float* betas, const float* etas, float4* tpack, int tpitch, long long tstride,
-                   hipStream_t s)
+                   int fpitch, const float* betas, const float* etas, void* tpack, int tpitch, long long tstride,
+                   int storage, hipStream_t s)
 {
     FinePtrs f;
     Params2 be;
@@ -293,33 +311,36 @@ void launch_tensor(int n, int W, int H, const float* const* J0, int jpitch, long
         be.beta[b] = betas[b];
         be.eta[b] = etas[b];
     }
-    hipLaunchKernelGGL(tensor_kernel, grid_for(W, H, n), dim3(64), 0, s, W, H, f, jpitch, jstride, flags, fpitch, be,
-                       tpack, tpitch, tstride);
+    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(tensor_kernel<S>, grid_for(W, H, n), dim3(64), 0, s, W, H, f, jpitch,
+                                               jstride, flags, fpitch, be, tpack, tpitch, tstride));
 }
 
 void launch_linearise(int n, int W, int H, int pitch, long long stride, const float* const* J0, int j0pitch,
                       long long j0stride, const float* J1, long long j1stride, const float2* gamma,
-                      const uint8_t* flags, float* u, float* u_w, float2* w, float2* gamma_w, float4* tpack,
-                      float* rho, int clip, int clip_only, float du_max, hipStream_t s)
+                      const uint8_t* flags, float* u, float* u_w, float2* w, float2* gamma_w, void* tpack,
+                      float* rho, int clip, int clip_only, float du_max, int storage, hipStream_t s)
 {
     FinePtrs f;
     for (int b = 0; b < n; ++b) f.p[b] = J0[b];
-    hipLaunchKernelGGL(linearise_kernel, grid_for(W, H, n), dim3(64), 0, s, W, H, pitch, stride, f, j0pitch, j0stride,
-                       J1, j1stride, gamma, flags, u, u_w, w, gamma_w, tpack, rho, clip, clip_only, du_max);
+    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(linearise_kernel<S>, grid_for(W, H, n), dim3(64), 0, s, W, H, pitch,
+                                               stride, f, j0pitch, j0stride, J1, j1stride, gamma, flags, u, u_w, w,
+                                               gamma_w, tpack, rho, clip, clip_only, du_max));
 }
 
 void launch_upsample(int n, int Wc, int Hc, int cpitch, long long cstride, const uint8_t* flags_c, int fcpitch,
                      const float* u_c, const float2* w_c, int fpitch, long long fstride, float* u_f, float2* w_f,
-                     float2* v_f, float2* p_f, float4* q_f, hipStream_t s)
+                     float2* v_f, void* p_f, void* q_f, int storage, hipStream_t s)
 {
-    hipLaunchKernelGGL(upsample_kernel, grid_for(2 * Wc, 2 * Hc, n), dim3(64), 0, s, Wc, Hc, cpitch, cstride, flags_c,
-                       fcpitch, u_c, w_c, fpitch, fstride, u_f, w_f, v_f, p_f, q_f);
+    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(upsample_kernel<S>, grid_for(2 * Wc, 2 * Hc, n), dim3(64), 0, s, Wc,
+                                               Hc, cpitch, cstride, flags_c, fcpitch, u_c, w_c, fpitch, fstride, u_f,
+                                               w_f, v_f, p_f, q_f));
 }
 
-void launch_zero_state(int n, int W, int H, int pitch, long long stride, float* u, float2* w, float2* v, float2* p,
-                       float4* q, hipStream_t s)
+void launch_zero_state(int n, int W, int H, int pitch, long long stride, float* u, float2* w, float2* v, void* p,
+                       void* q, int storage, hipStream_t s)
 {
-    hipLaunchKernelGGL(zero_state_kernel, grid_for(W, H, n), dim3(64), 0, s, W, pitch, stride, u, w, v, p, q);
+    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(zero_state_kernel<S>, grid_for(W, H, n), dim3(64), 0, s, W, pitch,
+                                               stride, u, w, v, p, q));
 }
 
 void launch_triangulate(int n, const RigGeom& g, int W, int H, int pitch, long long stride, const float* u,

@@ -16,6 +16,9 @@
 // PD_FUSED2 / PD_FUSED launches and one PD_PRIMAL_LAST launch (x^K).  Every
 // launch reads one copy of the state and writes the other.
 //
+// Storage: p, q and the tensor pack are read and written as FP32, FP16 or
+// BF16 (template S); u, v, rho_c and all arithmetic are FP32.
+//
 // Work decomposition: one 64-lane wavefront owns a strip of columns (62 for
 // the one-iteration modes: lanes 1..62, lanes 0 and 63 are the x-halo; 60 for
 // PD_FUSED2: lanes 2..61) and marches down 16 rows plus a halo above and
@@ -84,20 +87,20 @@ __device__ inline Row zero_row()
     return w;
 }
 
-template <bool TGV, bool PRIMAL>
+template <bool TGV, bool PRIMAL, int S>
 __device__ inline Row load_row(const PdArgs& a, long long base, int x, int r, bool in_x)
 {
     Row w = zero_row();
     if (in_x && r >= 0 && r < a.H) {
         const size_t o = base + (size_t)r * a.pitch + x;
         w.u = a.u_in[o];
-        w.p = a.p_in[o];
-        w.t = a.tpack[o];
+        w.p = ld2<S>(a.p_in, o);
+        w.t = ld4<S>(a.tpack, o);
         w.f = a.flags[(size_t)r * a.pitch + x];
         if (PRIMAL) w.rho = a.rho[o];
         if (TGV) {
             w.v = a.v_in[o];
-            w.q = a.q_in[o];
+            w.q = ld4<S>(a.q_in, o);
         }
     }
     return w;
@@ -221,7 +224,7 @@ __device__ inline int logical_block()
 }
 
 // One iteration (PD_FUSED) or its first / last half (PD_DUAL_FIRST, PD_PRIMAL_LAST).
-template <int MODE, bool TGV>
+template <int MODE, bool TGV, int S>
 __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
 {
     constexpr bool PRIMAL = MODE != PD_DUAL_FIRST;
@@ -254,13 +257,13 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
     float2 vb_prev = make_float2(0.f, 0.f);
     Above ab = {0.f, 0.f, 0.f, 0.f, 0.f};
     if (PRIMAL) {
-        const Row w = load_row<TGV, false>(a, base, x, y0 - 1, in_x);
+        const Row w = load_row<TGV, false, S>(a, base, x, y0 - 1, in_x);
         ab = above_of(w.p, w.q, w.t, w.f);
     }
 
     const int r_end = DUAL ? y1 : y1 - 1;       // last row visited (row y1 is the look-ahead)
     for (int r = y0; r <= r_end; ++r) {
-        const Row c = load_row<TGV, PRIMAL>(a, base, x, r, in_x);
+        const Row c = load_row<TGV, PRIMAL, S>(a, base, x, r, in_x);
         // primal step at row r: x^k from x^{k-1} and y^k
         float un = c.u;
         float2 vn = c.v;
@@ -285,8 +288,8 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
                 dual_step<TGV>(p_prev, q_prev, t_prev, f_prev, ub_prev, vb_prev, ub_r, vb_r, ub, vb, a0, a1,
                                a.sigma_scale, pn, qn);
                 const size_t o = base + (size_t)(r - 1) * a.pitch + x;
-                a.p_out[o] = pn;
-                if (TGV) a.q_out[o] = qn;
+                st2<S>(a.p_out, o, pn);
+                if (TGV) st4<S>(a.q_out, o, qn);
             }
         }
         // slide the window
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
 // read for A's first "above").  Column validity shrinks by one lane per
 // stage away from the wavefront's edges: A is exact on lanes 1..63, B on
 // 1..62, C on 2..62, D on 2..61 -- the owned lanes.
-template <bool TGV>
+template <bool TGV, int S>
 __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
 {
     const int logical = logical_block();
@@ -333,7 +336,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
     // iteration 1: "above" of row r-1, and row r-1 as B needs it
     Above ab1;
     {
-        const Row w = load_row<TGV, false>(a, base, x, y0 - 2, in_x);
+        const Row w = load_row<TGV, false, S>(a, base, x, y0 - 2, in_x);
         ab1 = above_of(w.p, w.q, w.t, w.f);
     }
     float2 p_m1 = make_float2(0.f, 0.f);
@@ -360,7 +363,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
         float un1 = 0.f, ub1 = 0.f;
         float2 vn1 = make_float2(0.f, 0.f), vb1 = make_float2(0.f, 0.f);
         if (r <= y1 + 1) {
-            c = load_row<TGV, true>(a, base, x, r, in_x);
+            c = load_row<TGV, true, S>(a, base, x, r, in_x);
             primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, a.tau_scale, un1, vn1);
             ub1 = un1 + a.theta * (un1 - c.u);
             vb1 = make_float2(vn1.x + a.theta * (vn1.x - c.v.x), vn1.y + a.theta * (vn1.y - c.v.y));
@@ -400,8 +403,8 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
                            pn, qn);
             if (owner) {
                 const size_t o = base + (size_t)(r - 3) * a.pitch + x;
-                a.p_out[o] = pn;
-                if (TGV) a.q_out[o] = qn;
+                st2<S>(a.p_out, o, pn);
+                if (TGV) st4<S>(a.q_out, o, qn);
             }
         }
         // slide the windows (deepest first)
@@ -432,22 +435,31 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
     }
 }
 
-template <int MODE, bool TGV>
+template <int MODE, bool TGV, int S>
 void launch_mode(const PdArgs& a, hipStream_t s)
 {
     const int tiles_x = (a.W + kCols - 1) / kCols;
     const int tiles_y = (a.H + kBY * kWaves - 1) / (kBY * kWaves);
     const int nb = tiles_x * tiles_y * a.n;
-    hipLaunchKernelGGL((pd_kernel<MODE, TGV>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
+    hipLaunchKernelGGL((pd_kernel<MODE, TGV, S>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
 }
 
-template <bool TGV>
+template <bool TGV, int S>
 void launch_fused2(const PdArgs& a, hipStream_t s)
 {
     const int tiles_x = (a.W + kCols2 - 1) / kCols2;
     const int tiles_y = (a.H + kBY2 * kWaves - 1) / (kBY2 * kWaves);
     const int nb = tiles_x * tiles_y * a.n;
-    hipLaunchKernelGGL((pd2_kernel<TGV>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
+    hipLaunchKernelGGL((pd2_kernel<TGV, S>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
+}
+
+template <bool TGV, int S>
+void launch_typed(const PdArgs& a, hipStream_t s)
+{
+    if (a.mode == PD_DUAL_FIRST) launch_mode<PD_DUAL_FIRST, TGV, S>(a, s);
+    else if (a.mode == PD_FUSED) launch_mode<PD_FUSED, TGV, S>(a, s);
+    else if (a.mode == PD_FUSED2) launch_fused2<TGV, S>(a, s);
+    else launch_mode<PD_PRIMAL_LAST, TGV, S>(a, s);
 }
 
 }  // namespace
@@ -455,15 +467,13 @@ void launch_fused2(const PdArgs& a, hipStream_t s)
 void launch_pd(const PdArgs& a, hipStream_t s)
 {
     if (a.tgv) {
-        if (a.mode == PD_DUAL_FIRST) launch_mode<PD_DUAL_FIRST, true>(a, s);
-        else if (a.mode == PD_FUSED) launch_mode<PD_FUSED, true>(a, s);
-        else if (a.mode == PD_FUSED2) launch_fused2<true>(a, s);
-        else launch_mode<PD_PRIMAL_LAST, true>(a, s);
+        if (a.storage == ST_F16) launch_typed<true, ST_F16>(a, s);
+        else if (a.storage == ST_BF16) launch_typed<true, ST_BF16>(a, s);
+        else launch_typed<true, ST_F32>(a, s);
     } else {
-        if (a.mode == PD_DUAL_FIRST) launch_mode<PD_DUAL_FIRST, false>(a, s);
-        else if (a.mode == PD_FUSED) launch_mode<PD_FUSED, false>(a, s);
-        else if (a.mode == PD_FUSED2) launch_fused2<false>(a, s);
-        else launch_mode<PD_PRIMAL_LAST, false>(a, s);
+        if (a.storage == ST_F16) launch_typed<false, ST_F16>(a, s);
+        else if (a.storage == ST_BF16) launch_typed<false, ST_BF16>(a, s);
+        else launch_typed<false, ST_F32>(a, s);
     }
 }
 

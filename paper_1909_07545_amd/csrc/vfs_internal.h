@@ -130,11 +130,72 @@ struct RigGeom {
     double eps;         // step along t' of the trajectory-field construction
 };
 
-// ----------------------------------------------------------------- per-level image descriptor
-struct Plane {
-    const float* ptr;
-    int pitch;          // elements
-};
+// ----------------------------------------------------------------- compact storage
+// The dual variables (p, q) and the tensor pack (t11, t12, t22, I_u) are
+// stored as 32-bit floats (ST_F32), IEEE half (ST_F16) or bfloat16
+// (ST_BF16); every update is computed in FP32.
+enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+__device__ inline uint16_t f32_to_h(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+__device__ inline float h_to_f32(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+// bfloat16 by round-to-nearest-even of the upper half of the FP32 bits
+__device__ inline uint16_t f32_to_bf(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+template <int S> __device__ inline uint16_t enc16(float x) { return S == ST_F16 ? f32_to_h(x) : f32_to_bf(x); }
+template <int S> __device__ inline float dec16(uint16_t b) { return S == ST_F16 ? h_to_f32(b) : bf_to_f32(b); }
+
+// The value a float takes once stored.
+template <int S> __device__ inline float as_stored(float x)
+{
+    if constexpr (S == ST_F32) return x;
+    else return dec16<S>(enc16<S>(x));
+}
+
+template <int S> __device__ inline float2 ld2(const void* base, size_t i)
+{
+    if constexpr (S == ST_F32) {
+        return static_cast<const float2*>(base)[i];
+    } else {
+        const uint32_t v = static_cast<const uint32_t*>(base)[i];
+        return make_float2(dec16<S>(uint16_t(v & 0xffffu)), dec16<S>(uint16_t(v >> 16)));
+    }
+}
+
+template <int S> __device__ inline float4 ld4(const void* base, size_t i)
+{
+    if constexpr (S == ST_F32) {
+        return static_cast<const float4*>(base)[i];
+    } else {
+        const uint2 v = static_cast<const uint2*>(base)[i];
+        return make_float4(dec16<S>(uint16_t(v.x & 0xffffu)), dec16<S>(uint16_t(v.x >> 16)),
+                           dec16<S>(uint16_t(v.y & 0xffffu)), dec16<S>(uint16_t(v.y >> 16)));
+    }
+}
+
+template <int S> __device__ inline void st2(void* base, size_t i, float2 f)
+{
+    if constexpr (S == ST_F32) {
+        static_cast<float2*>(base)[i] = f;
+    } else {
+        static_cast<uint32_t*>(base)[i] = uint32_t(enc16<S>(f.x)) | (uint32_t(enc16<S>(f.y)) << 16);
+    }
+}
+
+template <int S> __device__ inline void st4(void* base, size_t i, float4 f)
+{
+    if constexpr (S == ST_F32) {
+        static_cast<float4*>(base)[i] = f;
+    } else {
+        static_cast<uint2*>(base)[i] = make_uint2(uint32_t(enc16<S>(f.x)) | (uint32_t(enc16<S>(f.y)) << 16),
+                                                  uint32_t(enc16<S>(f.z)) | (uint32_t(enc16<S>(f.w)) << 16));
+    }
+}
 
 // ----------------------------------------------------------------- launchers
 // Set-up (double precision).
@@ -153,17 +214,17 @@ void launch_downsample(int n, int Wc, int Hc, const float* const* fine, int fpit
                        float* coarse, int cpitch, long long cstride, hipStream_t s);
 void launch_tensor(int n, int W, int H, const float* const* J0, int jpitch, long long jstride,
                    const uint8_t* flags, int fpitch, const float* betas, const float* etas,
-                   float4* tpack, int tpitch, long long tstride, hipStream_t s);
+                   void* tpack, int tpitch, long long tstride, int storage, hipStream_t s);
 void launch_linearise(int n, int W, int H, int pitch, long long stride, const float* const* J0,
                       int j0pitch, long long j0stride, const float* J1, long long j1stride,
                       const float2* gamma, const uint8_t* flags, float* u, float* u_w, float2* w,
-                      float2* gamma_w, float4* tpack, float* rho, int clip, int clip_only, float du_max,
-                      hipStream_t s);
+                      float2* gamma_w, void* tpack, float* rho, int clip, int clip_only, float du_max,
+                      int storage, hipStream_t s);
 void launch_upsample(int n, int Wc, int Hc, int cpitch, long long cstride, const uint8_t* flags_c,
                      int fcpitch, const float* u_c, const float2* w_c, int fpitch, long long fstride,
-                     float* u_f, float2* w_f, float2* v_f, float2* p_f, float4* q_f, hipStream_t s);
+                     float* u_f, float2* w_f, float2* v_f, void* p_f, void* q_f, int storage, hipStream_t s);
 void launch_zero_state(int n, int W, int H, int pitch, long long stride, float* u, float2* w, float2* v,
-                       float2* p, float4* q, hipStream_t s);
+                       void* p, void* q, int storage, hipStream_t s);
 void launch_triangulate(int n, const RigGeom& g, int W, int H, int pitch, long long stride,
                         const float* u, const float2* w, const uint8_t* flags, int fpitch,
                         float* const* u_out, float* const* w_out, float* const* depth_out,
@@ -175,9 +236,9 @@ struct PdArgs {
     int W, H, pitch;            // level size, element pitch of every plane
     long long stride;           // elements between pairs
     int n;                      // pairs
-    const float* u_in; const float2* v_in; const float2* p_in; const float4* q_in;
-    float* u_out; float2* v_out; float2* p_out; float4* q_out;
-    const float4* tpack;        // (t11, t12, t22, I_u)
+    const float* u_in; const float2* v_in; const void* p_in; const void* q_in;
+    float* u_out; float2* v_out; void* p_out; void* q_out;
+    const void* tpack;          // (t11, t12, t22, I_u)
     const float* rho;           // rho_c
     const uint8_t* flags;       // shared by all pairs (rig field)
     float alpha0, alpha1, lambda;
@@ -185,6 +246,7 @@ struct PdArgs {
     float tau_scale2, sigma_scale2, theta2;  // PD_FUSED2: iteration k + 1
     int mode;                   // PdMode
     int tgv;                    // 1: TGV-L1 (Eq. (10)); 0: TV-L1 (v = 0, no q)
+    int storage;                // Storage of p, q and the tensor pack
 };
 void launch_pd(const PdArgs& a, hipStream_t s);
 
