@@ -8,8 +8,13 @@ already resident in HBM.  Default workload: 8 pairs of 2048x2048
 Kannala-Brandt 200-degree fisheye images (seeded box-and-sphere rooms),
 7 levels x 15 warps x 200 iterations, FP32 TGV-L1.
 
+Then the serving study: 512 requests of three sizes and four rigs arrive as
+a Poisson stream; the same trace is served by the plain FP32 server (one pair
+at a time) and by the FP16 continuous-batching server, and the line reports
+p50 / p99 latency and pairs/s of both.
+
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
-[--config c5|c3|c2|c1] [--gpus 1] [--no-cpu-baseline]
+[--config c5|c3|c2|c1] [--gpus 1] [--no-cpu-baseline] [--no-serving]
 """
 import argparse
 import json
@@ -53,11 +58,21 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB device buffer (a plain copy kernel of known size, "
                          "for scaling hardware traffic counters)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving study")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving study (prints its JSON)")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-rates", type=lambda v: [float(x) for x in v.split(",")], default=[0.5, 0.8, 1.0, 1.5],
+                    help="arrival rates as fractions of the plain server's closed-loop pairs/s")
+    ap.add_argument("--serve-budget-gib", type=float, default=1.0)
+    ap.add_argument("--serve-slots", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the path shards "
               "by image pair across GPUs but no multi-GPU run is part of it", file=sys.stderr)
         sys.exit(2)
+    if args.serving_only:
+        print(json.dumps({"serving": serving_study(args)}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -154,6 +169,19 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, rig, pairs[0], tens[0], params, args.cpu_seconds)
 
+    serve = None
+    if not args.no_serving:
+        del outs, I0s, I1s
+        torch.cuda.empty_cache()
+        serve = serving_study(args)
+        at = min(serve["sweep"], key=lambda r: abs(r["rate_factor"] - 0.8))
+        serve["summary"] = {
+            "rate_pairs_per_s": at["rate_pairs_per_s"], "rate_factor": at["rate_factor"],
+            "fp32_plain": {k: at["plain_fp32"][k] for k in ("p50_ms", "p99_ms", "pairs_per_s")},
+            "fp16_batched": {k: at["batched_fp16"][k] for k in ("p50_ms", "p99_ms", "pairs_per_s")},
+            "closed_loop_pairs_per_s": {"fp32_plain": serve["closed_loop_plain_fp32"]["pairs_per_s"],
+                                        "fp16_batched": serve["closed_loop_batched_fp16"]["pairs_per_s"]}}
+
     line = {
         "metric": "primal-dual Mpix-iter/s", "value": round(value, 1), "unit": "Mpix-iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
@@ -166,8 +194,112 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp16_storage": fp16,
+        "serving": serve,
     }
     print(json.dumps(line), flush=True)
+
+
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, np.float64), q))
+
+
+def serving_study(args, log_prefix="serving"):
+    """Serving mix: 512 requests (320x240 / 640x480 / 1024x768 in the ratio
+    3:2:1, 4 rigs), Poisson arrivals at a fraction of the plain server's
+    closed-loop rate; the same trace replayed against the plain FP32 server
+    (first come first served, one pair at a time, eager launches) and the
+    FP16 continuous-batching server (size buckets, HBM budget, graph
+    replays).  Latency = completion seen by the server - arrival."""
+    import numpy as np
+    import torch
+
+    import paper_1909_07545_amd as vfs
+    from synth import configs, serving
+
+    sp = serving.spec()
+    t0 = time.time()
+    rigs = serving.serving_rigs(sp)
+    pool = serving.render_pool(rigs, 1, sp)
+    log(f"{log_prefix}: {len(pool)} pairs rendered in {time.time() - t0:.1f} s")
+    handles = {(r, s): vfs.Rig(rg["cam0"], rg["cam1"], rg["R"], rg["t"], rg["levels"])
+               for r, per in enumerate(rigs) for s, rg in enumerate(per)}
+    imgs = {k: (torch.from_numpy(v[0][0]).cuda(), torch.from_numpy(v[0][1]).cuda()) for k, v in pool.items()}
+    base = configs.solver_params(dict(levels=1, warps=sp["warps"], iters=sp["iters"]))
+    p32, p16 = dict(base, storage=0), dict(base, storage=1)
+    n = args.serve_requests
+    trace0 = serving.make_trace(1.0, n, sp)
+    outs = []
+    for q in trace0:
+        rg = handles[(q["rig"], q["size"])]
+        outs.append(dict(depth=torch.empty((rg.height, rg.width), device="cuda"),
+                         u=torch.empty((rg.height, rg.width), device="cuda"),
+                         valid=torch.empty((rg.height, rg.width), dtype=torch.uint8, device="cuda")))
+    torch.cuda.synchronize()
+    beta, eta = base["beta"], base["eta"]
+
+    def run(server_kw, params, trace, closed=False):
+        with vfs.Server(params, **server_kw) as srv:
+            # warm the buckets / workspaces (graph capture, first allocations)
+            for s in range(len(sp["sizes"])):
+                rg = handles[(0, s)]
+                o = dict(depth=torch.empty((rg.height, rg.width), device="cuda"))
+                srv.submit(rg, *imgs[(0, s)], o, beta, eta)
+            srv.wait_all(600.0)
+            tick0 = srv.stats()["ticks"]
+            tickets, t_sub = [], []
+            start = time.perf_counter()
+            for i, q in enumerate(trace):
+                if not closed:
+                    due = start + q["t"]
+                    while True:
+                        now = time.perf_counter()
+                        if now >= due:
+                            break
+                        if due - now > 2e-3:
+                            time.sleep(due - now - 1e-3)
+                rg = handles[(q["rig"], q["size"])]
+                t_sub.append(time.perf_counter())
+                tickets.append(srv.submit(rg, *imgs[(q["rig"], q["size"])], outs[i], beta, eta))
+            srv.wait_all(600.0)
+            lat = [srv.poll(t)[1] for t in tickets]
+            adm = [srv.times(t)[0] for t in tickets]
+            st = srv.stats()
+        done = [t + l for t, l in zip(t_sub, lat)]
+        span = max(done) - t_sub[0]
+        by_size = {}
+        for s, (W, H) in enumerate(sp["sizes"]):
+            ls = [l for l, q in zip(lat, trace) if q["size"] == s]
+            by_size[f"{W}x{H}"] = {"p50_ms": round(1e3 * _pct(ls, 50), 2), "p99_ms": round(1e3 * _pct(ls, 99), 2)}
+        return {"pairs_per_s": round(len(trace) / span, 2), "p50_ms": round(1e3 * _pct(lat, 50), 2),
+                "p99_ms": round(1e3 * _pct(lat, 99), 2), "mean_queue_ms": round(1e3 * float(np.mean(adm)), 2),
+                "by_size": by_size, "ticks": st["ticks"] - tick0, "peak_active": st["peak_active"],
+                "pool_peak_MiB": round(st["pool_peak_bytes"] / 2**20, 1)}
+
+    plain_kw = dict(mode="plain")
+    batched_kw = dict(mode="batched", hbm_budget_bytes=int(args.serve_budget_gib * 2**30),
+                      max_slots=args.serve_slots, use_graphs=True)
+    res = {}
+    res["closed_loop_plain_fp32"] = run(plain_kw, p32, trace0, closed=True)
+    rate0 = res["closed_loop_plain_fp32"]["pairs_per_s"]
+    log(f"{log_prefix}: plain FP32 closed loop {rate0} pairs/s")
+    res["closed_loop_batched_fp16"] = run(batched_kw, p16, trace0, closed=True)
+    log(f"{log_prefix}: batched FP16 closed loop {res['closed_loop_batched_fp16']['pairs_per_s']} pairs/s")
+    sweep = []
+    for f in args.serve_rates:
+        trace = serving.make_trace(f * rate0, n, sp)
+        row = {"rate_factor": f, "rate_pairs_per_s": round(f * rate0, 2)}
+        row["plain_fp32"] = run(plain_kw, p32, trace)
+        row["batched_fp16"] = run(batched_kw, p16, trace)
+        log(f"{log_prefix}: rate x{f}: plain p50/p99 {row['plain_fp32']['p50_ms']}/{row['plain_fp32']['p99_ms']} ms, "
+            f"batched {row['batched_fp16']['p50_ms']}/{row['batched_fp16']['p99_ms']} ms")
+        sweep.append(row)
+    res["sweep"] = sweep
+    res["workload"] = (f"{n} requests, sizes {sp['sizes']} ratio {sp['ratio']}, {sp['rigs']} KB rigs, "
+                       f"levels {sp['levels']} x {sp['warps']} warps x {sp['iters']} iters")
+    res["batched_config"] = {"hbm_budget_GiB": args.serve_budget_gib, "max_slots_per_size": args.serve_slots,
+                             "graphs": True, "storage": "fp16"}
+    return res
 
 
 def measured_traffic(config):

@@ -143,7 +143,9 @@ vfs_status vfs_solve(vfs_rig* rig, const float* I0, const float* I1, size_t pitc
                      const vfs_params* params, void* hip_stream);
 
 /* ---- Steps of the method on caller buffers (device), for step-by-step use
- * and testing; they use FP32 storage whatever params->storage says.
+ * and testing; they use FP32 storage whatever params->storage says.  They
+ * synchronise hip_stream before returning (they allocate a small temporary
+ * descriptor, and vfs_step_upsample / vfs_step_triangulate temporary planes).
  * Layout: row-major with a common row pitch of `pitch`
  * ELEMENTS (not bytes) for every plane; vector planes interleave their
  * components (float2 (x, y) per pixel for w, gamma, v, p; float4 for q and
@@ -192,6 +194,32 @@ vfs_status vfs_step_upsample(int width_c, int height_c, size_t pitch_c, const ui
 vfs_status vfs_step_triangulate(const vfs_rig* rig, size_t pitch, const float* w, float* depth, float* z,
                                 uint8_t* valid, void* hip_stream);
 
+/* Linearised energy of Eq. (10) at one level (A9):
+ *   E = sum over the mask of lambda |rho_c + u I_u| + alpha1 |T grad u - v|_2
+ *       + alpha0 |grad v|_F   (TV: v = 0, no last term),
+ * with the masked forward differences of the primal-dual iteration (flags
+ * bits 0-2).  Per-pixel terms in FP32, accumulated in FP64 in a fixed order
+ * (the same value on every run).  *energy (host) receives E. */
+vfs_status vfs_step_energy(int width, int height, size_t pitch, const float* tpack, const float* rho,
+                           const uint8_t* flags, const float* u, const float* v, const vfs_params* params,
+                           double* energy, void* hip_stream);
+
+/* vfs_step_pd with the energy trace: energy (host, iters + 1 doubles)
+ * receives E(x^0), E(x^1), ..., E(x^iters) of the primal iterates.  Runs one
+ * iteration per launch (the same iteration as vfs_step_pd; iters >= 1). */
+vfs_status vfs_step_pd_energy(int width, int height, size_t pitch, const float* tpack, const float* rho,
+                              const uint8_t* flags, float* u, float* v, float* p, float* q, float* scratch_u,
+                              float* scratch_v, float* scratch_p, float* scratch_q, const vfs_params* params,
+                              int iters, double* energy, void* hip_stream);
+
+/* Difference statistics of two float planes (device, pitch in elements) over
+ * the pixels whose flags bit 0 is set (all pixels if flags is NULL): mean and
+ * max of |a - b| and the pixel count (host outputs, each may be NULL); FP64
+ * fixed-order reduction on the device. */
+vfs_status vfs_diff_stats(int width, int height, size_t pitch, const float* a, const float* b,
+                          const uint8_t* flags, double* mean_abs, double* max_abs, long long* count,
+                          void* hip_stream);
+
 /* ---- Measurement: when enabled, vfs_solve_batch records HIP events on its
  * stream around the level-0 primal-dual launches that each carry two
  * iterations of Eq. (11) (the dominant kernel) and accumulates their elapsed
@@ -200,6 +228,89 @@ vfs_status vfs_step_triangulate(const vfs_rig* rig, size_t pitch, const float* w
  * (counts since the last reset). */
 vfs_status vfs_profile_enable(vfs_rig* rig, int enable);
 vfs_status vfs_profile_read(vfs_rig* rig, double* pd0_ms, long long* pd0_launches, int reset);
+
+/* ---- Serving: a request loop that batches stereo pairs of different
+ * sizes and rigs as they arrive (continuous batching).
+ *
+ * Requests are grouped by image size and level count into buckets of up to
+ * max_slots concurrent requests.  Each request admitted to a bucket owns a
+ * slot and its solve state from a device pool of hbm_budget_bytes; a
+ * request waits (in arrival order) until its bucket has a free slot and the
+ * pool has room, and its memory returns to the pool when it completes.  A
+ * bucket advances its requests together one warp step at a time: one step
+ * (a "tick") is one replay of a HIP graph captured at the bucket's creation
+ * (use_graphs = 1) or the same launches issued eagerly (use_graphs = 0);
+ * within a tick every request runs the stages of Algorithm 1 it needs at its
+ * own pyramid level and warp, so a request that arrives while others are
+ * mid-solve joins at the next tick.  Buckets run on their own streams and
+ * overlap on the device.  Each request's arithmetic is that of vfs_solve
+ * with the server's params (its levels are its rig's), so its outputs are
+ * the same as solving it alone.  Mode VFS_SERVE_PLAIN is the baseline: one
+ * request at a time in arrival order, eager launches.
+ *
+ * A scheduler thread owned by the server does all device work (on the
+ * device current at vfs_server_create).  submit / poll / times / wait_all /
+ * stats may be called from any thread.  The caller keeps the rigs, images
+ * and outputs of a request alive, and does not touch the outputs, until
+ * the request is done. */
+typedef struct vfs_server vfs_server;
+typedef enum { VFS_SERVE_BATCHED = 0, VFS_SERVE_PLAIN = 1 } vfs_serve_mode;
+typedef struct {
+    int mode;                  /* vfs_serve_mode */
+    size_t hbm_budget_bytes;   /* device pool for per-request solve state (batched mode) */
+    int max_slots;             /* concurrent requests per bucket, 1 .. VFS_MAX_BATCH */
+    int use_graphs;            /* batched mode: replay captured graphs (1) or launch eagerly (0) */
+} vfs_server_config;
+typedef struct {
+    long long ticks;           /* ticks (batched) or solves (plain) so far */
+    long long peak_active;     /* most requests in flight at once */
+    size_t pool_peak_bytes;    /* high-water mark of the pool (batched) */
+    int buckets;
+    long long joins;           /* admissions into a bucket whose other requests were mid-solve */
+    long long full_ticks;      /* ticks that ran start / level-change / finish stages */
+} vfs_server_counters;
+
+/* Defaults: batched, 1 GiB budget, 16 slots per bucket, graphs on. */
+vfs_status vfs_server_config_default(vfs_server_config* out);
+
+/* Create a server (and its scheduler thread).  params (host) holds the
+ * solver settings of every request (params->levels is ignored: each
+ * request uses its rig's level count); warps and iters must be >= 1.
+ * Batched mode allocates the pool here.
+ * Errors: VFS_E_INVALID, VFS_E_NOMEM, VFS_E_DEVICE. */
+vfs_status vfs_server_create(const vfs_server_config* cfg, const vfs_params* params, vfs_server** out);
+
+/* Device bytes of one request's solve state for a rig under this server. */
+vfs_status vfs_server_request_bytes(const vfs_server* server, const vfs_rig* rig, size_t* bytes);
+
+/* Queue one pair (device buffers as in vfs_solve; u_out, w_out, z_out and
+ * valid_out may be NULL) with its tensor parameters (Eq. (12)); the arrival
+ * time is stamped here.  *ticket (host) receives the request's id.
+ * Errors: VFS_E_INVALID, VFS_E_BUDGET (one request larger than the budget),
+ * or the error that stopped the server. */
+vfs_status vfs_server_submit(vfs_server* server, vfs_rig* rig, const float* I0, const float* I1,
+                             size_t pitch_bytes, float* u_out, float* w_out, float* depth_out, float* z_out,
+                             uint8_t* valid_out, double beta, double eta, unsigned long long* ticket);
+
+/* *done = 1 once the request's outputs are complete in device memory (the
+ * scheduler has seen its last launch finish); *latency_s (may be NULL) is
+ * then completion - arrival in seconds (host clock), else -1.
+ * Errors: VFS_E_INVALID (unknown ticket), VFS_E_DEVICE (the request failed). */
+vfs_status vfs_server_poll(vfs_server* server, unsigned long long ticket, int* done, double* latency_s);
+
+/* Admission and completion times of a request, seconds after its arrival
+ * (-1 if not yet). */
+vfs_status vfs_server_times(vfs_server* server, unsigned long long ticket, double* admit_s, double* done_s);
+
+/* Block until every submitted request is done, or timeout_s passes
+ * (VFS_E_DEVICE). */
+vfs_status vfs_server_wait_all(vfs_server* server, double timeout_s);
+
+vfs_status vfs_server_stats(vfs_server* server, vfs_server_counters* out);
+
+/* Finish the work in flight, stop the scheduler and free the server's
+ * device memory. */
+void vfs_server_destroy(vfs_server* server);
 
 /* Message of the calling thread's last error ("" if none). */
 const char* vfs_last_error(void);

@@ -37,6 +37,19 @@ class Params(ctypes.Structure):
                 ("du_max", ctypes.c_double), ("theta_gamma", ctypes.c_double), ("storage", ctypes.c_int)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int),
+                ("use_graphs", ctypes.c_int)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_longlong), ("peak_active", ctypes.c_longlong),
+                ("pool_peak_bytes", ctypes.c_size_t), ("buckets", ctypes.c_int), ("joins", ctypes.c_longlong),
+                ("full_ticks", ctypes.c_longlong)]
+
+
+SERVE_BATCHED, SERVE_PLAIN = 0, 1
+
 _lib = None
 _vp = ctypes.c_void_p
 
@@ -69,6 +82,21 @@ def lib():
         L.vfs_profile_enable.argtypes = [_vp, ctypes.c_int]
         L.vfs_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int]
         L.vfs_params_default.argtypes = [_vp]
+        L.vfs_step_energy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t] + [_vp] * 7 + [_vp]
+        L.vfs_step_pd_energy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t] + [_vp] * 11 + \
+            [_vp, ctypes.c_int, _vp, _vp]
+        L.vfs_diff_stats.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.vfs_server_config_default.argtypes = [_vp]
+        L.vfs_server_create.argtypes = [_vp, _vp, _vp]
+        L.vfs_server_request_bytes.argtypes = [_vp, _vp, _vp]
+        L.vfs_server_submit.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp,
+                                        ctypes.c_double, ctypes.c_double, _vp]
+        L.vfs_server_poll.argtypes = [_vp, ctypes.c_ulonglong, _vp, _vp]
+        L.vfs_server_times.argtypes = [_vp, ctypes.c_ulonglong, _vp, _vp]
+        L.vfs_server_wait_all.argtypes = [_vp, ctypes.c_double]
+        L.vfs_server_stats.argtypes = [_vp, _vp]
+        L.vfs_server_destroy.argtypes = [_vp]
+        L.vfs_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -210,6 +238,40 @@ def step_pd(tpack, rho, flags, u, v, p, q, params: dict, iters: int, stream=None
                              _stream(stream)))
 
 
+def step_energy(tpack, rho, flags, u, v, params: dict, stream=None) -> float:
+    """Linearised energy of Eq. (10) of the state (u, v) (vfs_step_energy)."""
+    H, W = u.shape
+    e = ctypes.c_double()
+    pp = _params(params)
+    _check(lib().vfs_step_energy(W, H, W, _ptr(tpack), _ptr(rho), _ptr(flags), _ptr(u), _ptr(v), ctypes.byref(pp),
+                                 ctypes.byref(e), _stream(stream)))
+    return e.value
+
+
+def step_pd_energy(tpack, rho, flags, u, v, p, q, params: dict, iters: int, stream=None):
+    """vfs_step_pd with the energy of every primal iterate: returns the
+    (iters + 1,) energies E(x^0) .. E(x^iters)."""
+    H, W = u.shape
+    su, sp = torch.empty_like(u), torch.empty_like(p)
+    sv = torch.empty_like(v) if v is not None else None
+    sq = torch.empty_like(q) if q is not None else None
+    pp = _params(params)
+    out = np.zeros(int(iters) + 1, np.float64)
+    _check(lib().vfs_step_pd_energy(W, H, W, _ptr(tpack), _ptr(rho), _ptr(flags), _ptr(u), _ptr(v), _ptr(p),
+                                    _ptr(q), _ptr(su), _ptr(sv), _ptr(sp), _ptr(sq), ctypes.byref(pp), int(iters),
+                                    out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return out
+
+
+def diff_stats(a, b, flags=None, stream=None):
+    """(mean, max, count) of |a - b| over flags bit 0 (all pixels if None)."""
+    H, W = a.shape
+    mean, mx, cnt = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
+    _check(lib().vfs_diff_stats(W, H, W, _ptr(a), _ptr(b), _ptr(flags), ctypes.byref(mean), ctypes.byref(mx),
+                                ctypes.byref(cnt), _stream(stream)))
+    return mean.value, mx.value, cnt.value
+
+
 def step_upsample(flags_c, u_c, w_c, u_f, w_f, stream=None):
     Hc, Wc = u_c.shape
     _check(lib().vfs_step_upsample(Wc, Hc, Wc, _ptr(flags_c), _ptr(u_c), _ptr(w_c), 2 * Wc, _ptr(u_f), _ptr(w_f),
@@ -230,3 +292,86 @@ def profile_read(rig: Rig, reset: bool = True):
     n = ctypes.c_longlong()
     _check(lib().vfs_profile_read(rig.handle, ctypes.byref(ms), ctypes.byref(n), int(reset)))
     return ms.value, n.value
+
+
+class Server:
+    """Request loop of vfs_server_create: ``mode`` "batched" (continuous
+    batching over size buckets, HBM-budget admission, graph replays) or
+    "plain" (one request at a time, arrival order, eager launches).  The
+    object keeps each request's tensors alive until the request is done."""
+
+    def __init__(self, params: dict, mode: str = "batched", hbm_budget_bytes: int = 1 << 30,
+                 max_slots: int = 16, use_graphs: bool = True):
+        cfg = ServerConfig()
+        _check(lib().vfs_server_config_default(ctypes.byref(cfg)))
+        cfg.mode = SERVE_PLAIN if mode == "plain" else SERVE_BATCHED
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.max_slots = int(max_slots)
+        cfg.use_graphs = int(bool(use_graphs))
+        p = _params(dict(params, levels=params.get("levels", 1)))
+        self._h = ctypes.c_void_p()
+        _check(lib().vfs_server_create(ctypes.byref(cfg), ctypes.byref(p), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def request_bytes(self, rig: Rig) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().vfs_server_request_bytes(self._h, rig.handle, ctypes.byref(b)))
+        return b.value
+
+    def submit(self, rig: Rig, I0, I1, out: dict, beta: float, eta: float) -> int:
+        """Queue one pair; ``out`` holds pre-allocated output tensors (keys u,
+        w, depth, z, valid; u/w/z/valid may be missing).  Returns the ticket."""
+        H, W = rig.height, rig.width
+        _dev_f32(I0, (H, W))
+        _dev_f32(I1, (H, W))
+        _dev_f32(out["depth"], (H, W))
+        tk = ctypes.c_ulonglong()
+        _check(lib().vfs_server_submit(self._h, rig.handle, _ptr(I0), _ptr(I1), 4 * W, _ptr(out.get("u")),
+                                       _ptr(out.get("w")), _ptr(out["depth"]), _ptr(out.get("z")),
+                                       _ptr(out.get("valid")), float(beta), float(eta), ctypes.byref(tk)))
+        self._keep[tk.value] = (rig, I0, I1, out)
+        return tk.value
+
+    def poll(self, ticket: int):
+        """(done, latency in seconds or None)."""
+        done = ctypes.c_int()
+        lat = ctypes.c_double()
+        _check(lib().vfs_server_poll(self._h, ctypes.c_ulonglong(ticket), ctypes.byref(done), ctypes.byref(lat)))
+        if done.value:
+            self._keep.pop(ticket, None)
+            return True, lat.value
+        return False, None
+
+    def times(self, ticket: int):
+        """(admission, completion) in seconds after arrival (-1: not yet)."""
+        a, d = ctypes.c_double(), ctypes.c_double()
+        _check(lib().vfs_server_times(self._h, ctypes.c_ulonglong(ticket), ctypes.byref(a), ctypes.byref(d)))
+        return a.value, d.value
+
+    def wait_all(self, timeout_s: float = 600.0):
+        _check(lib().vfs_server_wait_all(self._h, float(timeout_s)))
+        self._keep.clear()
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(lib().vfs_server_stats(self._h, ctypes.byref(c)))
+        return dict(ticks=c.ticks, peak_active=c.peak_active, pool_peak_bytes=c.pool_peak_bytes,
+                    buckets=c.buckets, joins=c.joins, full_ticks=c.full_ticks)
+
+    def close(self):
+        if self._h:
+            lib().vfs_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -2,21 +2,16 @@
 // level-0 primal-dual timing.  Host code only enqueues work; the solve never
 // waits on the device.
 #include <math.h>
-#include <stdarg.h>
-#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <new>
-#include <utility>
-#include <vector>
 
-#include "../../include/vfs.h"
-#include "vfs_internal.h"
+#include "runtime.h"
 
 using namespace vfs;
 
-namespace {
+namespace vfs {
 
 thread_local char g_err[512] = "";
 
@@ -29,15 +24,17 @@ vfs_status fail(vfs_status st, const char* fmt, ...)
     return st;
 }
 
+}  // namespace vfs
+
 #define HIP_OK(call)                                                                              \
     do {                                                                                          \
         hipError_t e_ = (call);                                                                   \
         if (e_ != hipSuccess) return fail(VFS_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-constexpr double kPi = 3.14159265358979323846;
+namespace {
 
-int round_pitch(int w) { return (w + 63) / 64 * 64; }
+constexpr double kPi = 3.14159265358979323846;
 
 // Largest angle of the grid i*pi/4096 up to which the radial map increases.
 double theta_limit(const vfs_camera& c)
@@ -80,122 +77,125 @@ Cam to_cam(const vfs_camera& c)
     return o;
 }
 
-struct Level {
-    int W, H, pitch;
-    size_t plane;       // pitch * H
-};
-
 }  // namespace
 
-struct vfs_rig {
-    RigGeom geom;
-    int L = 0;
-    Level lv[kMaxLevels];
-    float2* gamma[kMaxLevels] = {};
-    uint8_t* flags[kMaxLevels] = {};
-    float2* calib = nullptr;
-    int device = 0;
-
-    // workspace for up to `cap` pairs
-    int cap = 0;
-    void* ws = nullptr;
-    size_t n0 = 0;              // elements of a level-0 plane
-    size_t sj0 = 0, sj1 = 0;    // floats per pair of the J0 (levels >= 1) and J1 pyramids
-    size_t off0[kMaxLevels] = {}, off1[kMaxLevels] = {};
-    float* J0 = nullptr;
-    float* J1 = nullptr;
-    float* u[2] = {};
-    float* uw = nullptr;
-    float2* w[2] = {};
-    float2* v[2] = {};
-    void* p[2] = {};            // float2 / 2 x 16-bit per pixel, by storage
-    void* q[2] = {};            // float4 / 4 x 16-bit
-    void* tpack = nullptr;      // float4 / 4 x 16-bit
-    float* rho = nullptr;
-    float2* gw = nullptr;
-
-    // level-0 primal-dual timing
-    bool profile = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-    long long launches = 0;
-    double ms = 0.0;
-    hipStream_t last_stream = nullptr;
-
-    ~vfs_rig()
-    {
-        for (int l = 0; l < kMaxLevels; ++l) {
-            if (gamma[l]) (void)hipFree(gamma[l]);
-            if (flags[l]) (void)hipFree(flags[l]);
-        }
-        if (calib) (void)hipFree(calib);
-        if (ws) (void)hipFree(ws);
-        for (auto& e : events) {
-            (void)hipEventDestroy(e.first);
-            (void)hipEventDestroy(e.second);
-        }
-    }
-};
-
-namespace {
-
-vfs_status ensure_workspace(vfs_rig* r, int n)
+vfs_rig::~vfs_rig()
 {
-    if (n <= r->cap) return VFS_OK;
-    if (r->ws) {
-        HIP_OK(hipFree(r->ws));
-        r->ws = nullptr;
-        r->cap = 0;
+    for (int l = 0; l < vfs::kMaxLevels; ++l) {
+        if (gamma[l]) (void)hipFree(gamma[l]);
+        if (flags[l]) (void)hipFree(flags[l]);
     }
-    const Level& l0 = r->lv[0];
-    r->n0 = l0.plane;
-    size_t sj0 = 0, sj1 = 0;
-    for (int l = 0; l < r->L; ++l) {
-        r->off1[l] = sj1;
-        sj1 += r->lv[l].plane;
-        r->off0[l] = sj0;
-        if (l > 0) sj0 += r->lv[l].plane;
+    if (calib) (void)hipFree(calib);
+    if (geom_dev) (void)hipFree(geom_dev);
+    for (auto& e : events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
     }
-    r->sj0 = sj0;
-    r->sj1 = sj1;
-    // float counts per pair: J0 (levels >= 1), J1, u x2, uw, w x2 (2), v x2 (2), p x2 (2),
-    // q x2 (4), tpack (4), rho, gw (2)
-    const size_t per = sj0 + sj1 + r->n0 * (2 + 1 + 4 + 4 + 4 + 8 + 4 + 1 + 2);
-    const size_t bytes = per * sizeof(float) * size_t(n) + 4096;
-    void* m = nullptr;
-    if (hipMalloc(&m, bytes) != hipSuccess)
-        return fail(VFS_E_NOMEM, "workspace of %zu bytes for %d pairs", bytes, n);
-    r->ws = m;
-    r->cap = n;
-    float* f = static_cast<float*>(m);
-    size_t at = 0;
-    auto take = [&](size_t floats_per_pair) {
-        float* ptr = f + at;
-        at += floats_per_pair * size_t(n);
-        return ptr;
-    };
-    r->J0 = take(sj0);
-    r->J1 = take(sj1);
-    r->u[0] = take(r->n0);
-    r->u[1] = take(r->n0);
-    r->uw = take(r->n0);
-    r->w[0] = reinterpret_cast<float2*>(take(2 * r->n0));
-    r->w[1] = reinterpret_cast<float2*>(take(2 * r->n0));
-    r->v[0] = reinterpret_cast<float2*>(take(2 * r->n0));
-    r->v[1] = reinterpret_cast<float2*>(take(2 * r->n0));
-    r->p[0] = take(2 * r->n0);
-    r->p[1] = take(2 * r->n0);
-    r->q[0] = take(4 * r->n0);
-    r->q[1] = take(4 * r->n0);
-    r->tpack = take(4 * r->n0);
-    r->rho = take(r->n0);
-    r->gw = reinterpret_cast<float2*>(take(2 * r->n0));
-    return VFS_OK;
 }
 
-// Scalar schedule of the over-relaxation (theta) and the step factors.
-struct Sched {
-    std::vector<float> s, theta;
-};
+namespace vfs {
+
+Geometry make_geometry(int W, int H, int L)
+{
+    Geometry g{};
+    g.L = L;
+    long long off = 0;
+    for (int l = 0; l < L; ++l) {
+        g.W[l] = W >> l;
+        g.H[l] = H >> l;
+        g.pitch[l] = ((W >> l) + 63) / 64 * 64;
+        g.off[l] = off;
+        off += (long long)g.pitch[l] * g.H[l];
+    }
+    return g;
+}
+
+PairLayout make_layout(const Geometry& g, int storage, bool tgv)
+{
+    PairLayout y{};
+    y.storage = storage;
+    y.tgv = tgv;
+    const size_t st = stacked_elems(g), one = plane_elems(g, 0);
+    const size_t e2 = storage == ST_F32 ? 8 : 4, e4 = storage == ST_F32 ? 16 : 8;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = at;
+        at += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    y.J0 = take(st * 4);
+    y.J1 = take(st * 4);
+    for (int k = 0; k < 2; ++k) y.u[k] = take(st * 4);
+    for (int k = 0; k < 2; ++k) y.p[k] = take(st * e2);
+    if (tgv) {
+        for (int k = 0; k < 2; ++k) y.v[k] = take(st * 8);
+        for (int k = 0; k < 2; ++k) y.q[k] = take(st * e4);
+    }
+    y.w = take(st * 8);
+    y.uw = take(one * 4);
+    y.gw = take(one * 8);
+    y.tpack = take(one * e4);
+    y.rho = take(one * 4);
+    y.bytes = at;
+    return y;
+}
+
+void bind_state(Slot& sl, void* region, const PairLayout& y)
+{
+    char* m = static_cast<char*>(region);
+    sl.J0 = reinterpret_cast<float*>(m + y.J0);
+    sl.J1 = reinterpret_cast<float*>(m + y.J1);
+    for (int k = 0; k < 2; ++k) {
+        sl.u[k] = reinterpret_cast<float*>(m + y.u[k]);
+        sl.p[k] = m + y.p[k];
+        sl.v[k] = y.tgv ? reinterpret_cast<float2*>(m + y.v[k]) : nullptr;
+        sl.q[k] = y.tgv ? static_cast<void*>(m + y.q[k]) : nullptr;
+    }
+    sl.w = reinterpret_cast<float2*>(m + y.w);
+    sl.uw = reinterpret_cast<float*>(m + y.uw);
+    sl.gw = reinterpret_cast<float2*>(m + y.gw);
+    sl.tpack = m + y.tpack;
+    sl.rho = reinterpret_cast<float*>(m + y.rho);
+}
+
+void bind_rig(Slot& sl, const vfs_rig* r)
+{
+    for (int l = 0; l < kMaxLevels; ++l) {
+        sl.gamma[l] = l < r->g.L ? r->gamma[l] : nullptr;
+        sl.flags[l] = l < r->g.L ? r->flags[l] : nullptr;
+    }
+    sl.calib = r->calib;
+    sl.geom = r->geom_dev;
+}
+
+void Workspace::release()
+{
+    if (mem) (void)hipFree(mem);
+    if (slots) (void)hipFree(slots);
+    mem = nullptr;
+    slots = nullptr;
+    cap = 0;
+}
+
+vfs_status ensure_workspace(Workspace& ws, const Geometry& g, int n, int storage, bool tgv)
+{
+    bool same = ws.mem && ws.cap >= n && ws.g.L == g.L && ws.lay.storage == storage && ws.lay.tgv == tgv;
+    for (int l = 0; same && l < g.L; ++l) same = ws.g.W[l] == g.W[l] && ws.g.H[l] == g.H[l];
+    if (same) return VFS_OK;
+    ws.release();
+    ws.g = g;
+    ws.lay = make_layout(g, storage, tgv);
+    const size_t bytes = ws.lay.bytes * size_t(n);
+    void* m = nullptr;
+    if (hipMalloc(&m, bytes) != hipSuccess) return fail(VFS_E_NOMEM, "workspace of %zu bytes for %d pairs", bytes, n);
+    ws.mem = m;
+    if (hipMalloc(&ws.slots, sizeof(Slot) * kMaxBatch) != hipSuccess) {
+        ws.release();
+        return fail(VFS_E_NOMEM, "slot descriptors");
+    }
+    ws.cap = n;
+    return VFS_OK;
+}
 
 Sched schedule(const vfs_params& p)
 {
@@ -227,26 +227,23 @@ vfs_status check_params(const vfs_params* p)
     return VFS_OK;
 }
 
-// K primal-dual iterations from a warp start on the state index pair (iu, ip);
-// the indices are updated to those holding the result.  Returns the number of
-// two-iteration launches, which ev0 / ev1 (if given) bracket.
-int run_pd(PdArgs base, const Sched& sc, int K, float* const* u, float2* const* v, void* const* p,
-           void* const* q, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
+    iu = base.lc.iu;
+    ip = base.lc.ip;
     if (K <= 0) return 0;
-    auto bind = [&](PdArgs& a) {
-        a.u_in = u[iu]; a.v_in = v ? v[iu] : nullptr; a.p_in = p[ip]; a.q_in = q ? q[ip] : nullptr;
-        a.u_out = u[1 - iu]; a.v_out = v ? v[1 - iu] : nullptr;
-        a.p_out = p[1 - ip]; a.q_out = q ? q[1 - ip] : nullptr;
-    };
     PdArgs a = base;
+    auto go = [&]() {
+        a.lc.iu = iu;
+        a.lc.ip = ip;
+        launch_pd(a, s);
+    };
     a.mode = PD_DUAL_FIRST;
     a.tau_scale = 1.f;
     a.sigma_scale = 1.f / sc.s[0];
     a.theta = 1.f;
-    bind(a);
-    launch_pd(a, s);
-    ip = 1 - ip;
+    go();
+    ip ^= 1;
     // iterations 1 .. K-1: an odd one alone, then pairs in one pass each
     int k = 1;
     if ((K - 1) % 2) {
@@ -254,10 +251,9 @@ int run_pd(PdArgs base, const Sched& sc, int K, float* const* u, float2* const* 
         a.tau_scale = sc.s[k - 1];
         a.theta = sc.theta[k - 1];
         a.sigma_scale = 1.f / sc.s[k];
-        bind(a);
-        launch_pd(a, s);
-        iu = 1 - iu;
-        ip = 1 - ip;
+        go();
+        iu ^= 1;
+        ip ^= 1;
         ++k;
     }
     if (ev0) (void)hipEventRecord(ev0, s);
@@ -270,23 +266,90 @@ int run_pd(PdArgs base, const Sched& sc, int K, float* const* u, float2* const* 
         a.tau_scale2 = sc.s[k];
         a.theta2 = sc.theta[k];
         a.sigma_scale2 = 1.f / sc.s[k + 1];
-        bind(a);
-        launch_pd(a, s);
-        iu = 1 - iu;
-        ip = 1 - ip;
+        go();
+        iu ^= 1;
+        ip ^= 1;
     }
     if (ev1) (void)hipEventRecord(ev1, s);
     a.mode = PD_PRIMAL_LAST;
     a.tau_scale = sc.s[K - 1];
     a.sigma_scale = 1.f;
     a.theta = 1.f;
-    bind(a);
-    launch_pd(a, s);
-    iu = 1 - iu;
+    go();
+    iu ^= 1;
     return pairs;
 }
 
-}  // namespace
+PdArgs pd_args(const Launch& lc, const vfs_params& params)
+{
+    PdArgs pa{};
+    pa.lc = lc;
+    pa.alpha0 = float(params.alpha0);
+    pa.alpha1 = float(params.alpha1);
+    pa.lambda = float(params.lambda);
+    pa.tgv = params.reg == VFS_TGV ? 1 : 0;
+    pa.storage = params.storage;
+    return pa;
+}
+
+// Whole method (Algorithm 1 in the pyramid of Sec. IV-B after the
+// pre-rotation of Sec. IV-A, then the triangulation of Sec. III-D).
+vfs_status solve_slots(const Slot* slots, int n, const Geometry& g, const vfs_params& params, hipStream_t s,
+                       vfs_rig* prof)
+{
+    const int L = g.L;
+    const bool tgv = params.reg == VFS_TGV;
+    const int st = params.storage;
+    Launch lc{};
+    lc.slots = slots;
+    lc.n = n;
+    lc.g = g;
+    auto at = [&](int l) {
+        lc.lev = l;
+        lc.gl = l;
+    };
+    // A1, A2: level 0 of the pyramids (pre-rotation), then levels 1 .. L-1
+    at(0);
+    launch_prerotate(lc, s);
+    for (int l = 1; l < L; ++l) {
+        at(l);
+        launch_downsample(lc, s);
+    }
+    const Sched sc = schedule(params);
+    for (int l = L - 1; l >= 0; --l) {
+        at(l);
+        // A3: tensor of the level (Eq. (12)); A7: state of the level
+        launch_tensor(lc, st, s);
+        if (l == L - 1) launch_zero_state(lc, tgv ? 1 : 0, st, s);
+        else launch_upsample(lc, tgv ? 1 : 0, st, s);
+        for (int wv = 0; wv <= params.warps; ++wv) {
+            // A4 (+A6 of the previous warp): clip, accumulate, linearise
+            const bool last = wv == params.warps;
+            if (last && wv == 0) break;
+            launch_linearise(lc, wv > 0 ? 1 : 0, last ? 1 : 0, float(params.du_max), st, s);
+            if (last) break;
+            // A5: K primal-dual iterations (Eq. (11))
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (prof && prof->profile && l == 0 && params.iters >= 3) {
+                if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+                    return fail(VFS_E_DEVICE, "hipEventCreate");
+                prof->events.emplace_back(e0, e1);
+            }
+            int iu, ip;
+            const int np = run_pd(pd_args(lc, params), sc, params.iters, iu, ip, s, e0, e1);
+            lc.iu = iu;
+            lc.ip = ip;
+            if (e0) prof->launches += np;
+        }
+    }
+    // A8: triangulation and outputs
+    at(0);
+    launch_triangulate(lc, s);
+    if (hipGetLastError() != hipSuccess) return fail(VFS_E_DEVICE, "kernel launch failed");
+    return VFS_OK;
+}
+
+}  // namespace vfs
 
 extern "C" {
 
@@ -349,30 +412,25 @@ vfs_status vfs_rig_create(const vfs_camera* cam0, const vfs_camera* cam1, const 
     g.half1 = 0.5 * cam1->fov_deg * kPi / 180.0;
     g.cos_guard = cos(2.0 * kPi / 180.0);
     g.eps = 1e-6;
-    r->L = levels;
-    for (int l = 0; l < levels; ++l) {
-        Level& lv = r->lv[l];
-        lv.W = cam0->width >> l;
-        lv.H = cam0->height >> l;
-        lv.pitch = round_pitch(lv.W);
-        lv.plane = size_t(lv.pitch) * lv.H;
-    }
+    r->g = make_geometry(cam0->width, cam0->height, levels);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     auto cleanup = [&](vfs_status e) { delete r; return e; };
     if (hipGetDevice(&r->device) != hipSuccess) return cleanup(fail(VFS_E_DEVICE, "hipGetDevice failed"));
+    if (hipMalloc(&r->geom_dev, sizeof(RigGeom)) != hipSuccess) return cleanup(fail(VFS_E_NOMEM, "rig geometry"));
+    if (hipMemcpyAsync(r->geom_dev, &g, sizeof(RigGeom), hipMemcpyHostToDevice, s) != hipSuccess)
+        return cleanup(fail(VFS_E_DEVICE, "copying rig geometry"));
     for (int l = 0; l < levels; ++l) {
-        const Level& lv = r->lv[l];
-        if (hipMalloc(&r->gamma[l], lv.plane * sizeof(float2)) != hipSuccess ||
-            hipMalloc(&r->flags[l], lv.plane) != hipSuccess)
+        const size_t plane = plane_elems(r->g, l);
+        if (hipMalloc(&r->gamma[l], plane * sizeof(float2)) != hipSuccess || hipMalloc(&r->flags[l], plane) != hipSuccess)
             return cleanup(fail(VFS_E_NOMEM, "rig fields"));
-        if (hipMemsetAsync(r->gamma[l], 0, lv.plane * sizeof(float2), s) != hipSuccess ||
-            hipMemsetAsync(r->flags[l], 0, lv.plane, s) != hipSuccess)
+        if (hipMemsetAsync(r->gamma[l], 0, plane * sizeof(float2), s) != hipSuccess ||
+            hipMemsetAsync(r->flags[l], 0, plane, s) != hipSuccess)
             return cleanup(fail(VFS_E_DEVICE, "clearing rig fields"));
-        launch_level_fields(g, l, r->gamma[l], r->flags[l], lv.pitch, s);
+        launch_level_fields(g, l, r->gamma[l], r->flags[l], r->g.pitch[l], s);
     }
-    if (hipMalloc(&r->calib, r->lv[0].plane * sizeof(float2)) != hipSuccess)
+    if (hipMalloc(&r->calib, plane_elems(r->g, 0) * sizeof(float2)) != hipSuccess)
         return cleanup(fail(VFS_E_NOMEM, "calibration field"));
-    launch_calibration(g, r->calib, r->lv[0].pitch, s);
+    launch_calibration(g, r->calib, r->g.pitch[0], s);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return cleanup(fail(VFS_E_DEVICE, "rig set-up kernels failed"));
     *out = r;
@@ -385,14 +443,14 @@ vfs_status vfs_rig_field(const vfs_rig* r, int level, int which, void* dst, size
 {
     g_err[0] = 0;
     if (!r || !dst) return fail(VFS_E_INVALID, "NULL argument");
-    if (level < 0 || level >= r->L) return fail(VFS_E_INVALID, "level out of range");
+    if (level < 0 || level >= r->g.L) return fail(VFS_E_INVALID, "level out of range");
     if (which < 0 || which > 2 || (which == 1 && level != 0)) return fail(VFS_E_INVALID, "bad field");
-    const Level& lv = r->lv[level];
+    const int W = r->g.W[level], H = r->g.H[level], pitch = r->g.pitch[level];
     const size_t esz = which == 2 ? 1 : sizeof(float2);
-    if (pitch_bytes < esz * lv.W) return fail(VFS_E_INVALID, "pitch too small");
+    if (pitch_bytes < esz * W) return fail(VFS_E_INVALID, "pitch too small");
     const void* src = which == 0 ? (const void*)r->gamma[level] : which == 1 ? (const void*)r->calib
                                                                             : (const void*)r->flags[level];
-    HIP_OK(hipMemcpy2DAsync(dst, pitch_bytes, src, esz * lv.pitch, esz * lv.W, lv.H, hipMemcpyDeviceToDevice,
+    HIP_OK(hipMemcpy2DAsync(dst, pitch_bytes, src, esz * pitch, esz * W, H, hipMemcpyDeviceToDevice,
                             static_cast<hipStream_t>(hip_stream)));
     return VFS_OK;
 }
@@ -407,11 +465,10 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
     if (n < 1 || n > kMaxBatch) return fail(VFS_E_INVALID, "n must be in [1, %d]", kMaxBatch);
     vfs_status st = check_params(params);
     if (st) return st;
-    if (params->levels != r->L) return fail(VFS_E_INVALID, "params->levels (%d) differs from the rig's (%d)",
-                                            params->levels, r->L);
-    const Level& l0 = r->lv[0];
-    if (pitch_bytes % sizeof(float) || pitch_bytes < sizeof(float) * l0.W)
-        return fail(VFS_E_INVALID, "bad pitch");
+    if (params->levels != r->g.L)
+        return fail(VFS_E_INVALID, "params->levels (%d) differs from the rig's (%d)", params->levels, r->g.L);
+    const int W = r->g.W[0];
+    if (pitch_bytes % sizeof(float) || pitch_bytes < sizeof(float) * W) return fail(VFS_E_INVALID, "bad pitch");
     if (!I0 || !I1 || !u_out || !w_out || !depth_out) return fail(VFS_E_INVALID, "NULL array argument");
     for (int b = 0; b < n; ++b) {
         if (!I0[b] || !I1[b] || !u_out[b] || !w_out[b] || !depth_out[b])
@@ -419,104 +476,29 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
         if ((betas && !(betas[b] >= 0.0)) || (etas && !(etas[b] > 0.0)))
             return fail(VFS_E_INVALID, "bad tensor parameters for pair %d", b);
     }
-    st = ensure_workspace(r, n);
+    st = ensure_workspace(r->ws, r->g, n, params->storage, params->reg == VFS_TGV);
     if (st) return st;
-
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     r->last_stream = s;
-    const int ip_caller = int(pitch_bytes / sizeof(float));
-    const long long N0 = (long long)r->n0;
-    const int L = r->L;
-    const bool tgv = params->reg == VFS_TGV;
-
-    // A1: pre-rotation of I1 (Sec. IV-A) into level 0 of the J1 pyramid
-    PairPtrs in1;
-    in1.in_pitch = ip_caller;
-    for (int b = 0; b < n; ++b) in1.in[b] = I1[b];
-    launch_prerotate(in1, n, l0.W, l0.H, r->calib, l0.pitch, r->J1 + r->off1[0], l0.pitch, (long long)r->sj1, s);
-
-    // A2: pyramids (Sec. IV-B); level 0 of J0 is the caller's image
-    const float* j0[kMaxLevels][kMaxBatch];
-    int j0pitch[kMaxLevels];
-    for (int b = 0; b < n; ++b) j0[0][b] = I0[b];
-    j0pitch[0] = ip_caller;
-    for (int l = 1; l < L; ++l) {
-        const Level& lv = r->lv[l];
-        for (int b = 0; b < n; ++b) j0[l][b] = r->J0 + b * r->sj0 + r->off0[l];
-        j0pitch[l] = lv.pitch;
-        launch_downsample(n, lv.W, lv.H, j0[l - 1], j0pitch[l - 1], 0, r->J0 + r->off0[l], lv.pitch,
-                          (long long)r->sj0, s);
-        const float* f1[kMaxBatch];
-        for (int b = 0; b < n; ++b) f1[b] = r->J1 + b * r->sj1 + r->off1[l - 1];
-        launch_downsample(n, lv.W, lv.H, f1, r->lv[l - 1].pitch, 0, r->J1 + r->off1[l], lv.pitch,
-                          (long long)r->sj1, s);
-    }
-
-    float bet[kMaxBatch], et[kMaxBatch];
+    const int ip = int(pitch_bytes / sizeof(float));
     for (int b = 0; b < n; ++b) {
-        bet[b] = float(betas ? betas[b] : params->beta);
-        et[b] = float(etas ? etas[b] : params->eta);
+        Slot sl{};
+        sl.I0 = I0[b];
+        sl.I1 = I1[b];
+        sl.in_pitch = ip;
+        sl.out_pitch = ip;
+        sl.u_out = u_out[b];
+        sl.w_out = w_out[b];
+        sl.depth_out = depth_out[b];
+        sl.z_out = z_out ? z_out[b] : nullptr;
+        sl.valid_out = valid_out ? valid_out[b] : nullptr;
+        bind_rig(sl, r);
+        bind_state(sl, static_cast<char*>(r->ws.mem) + size_t(b) * r->ws.lay.bytes, r->ws.lay);
+        sl.beta = float(betas ? betas[b] : params->beta);
+        sl.eta = float(etas ? etas[b] : params->eta);
+        launch_write_slot(sl, r->ws.slots + b, s);
     }
-    const Sched sc = schedule(*params);
-    int iu = 0, ip = 0, iw = 0;
-
-    for (int l = L - 1; l >= 0; --l) {
-        const Level& lv = r->lv[l];
-        // A3: tensor of the level (Eq. (12))
-        launch_tensor(n, lv.W, lv.H, j0[l], j0pitch[l], 0, r->flags[l], lv.pitch, bet, et, r->tpack, lv.pitch, N0,
-                      params->storage, s);
-        // A7: state of the level: zero at the coarsest, else transferred from level l+1
-        if (l == L - 1) {
-            launch_zero_state(n, lv.W, lv.H, lv.pitch, N0, r->u[iu], r->w[iw], tgv ? r->v[iu] : nullptr, r->p[ip],
-                              tgv ? r->q[ip] : nullptr, params->storage, s);
-        } else {
-            const Level& lc = r->lv[l + 1];
-            launch_upsample(n, lc.W, lc.H, lc.pitch, N0, r->flags[l + 1], lc.pitch, r->u[iu], r->w[iw], lv.pitch, N0,
-                            r->u[1 - iu], r->w[1 - iw], tgv ? r->v[1 - iu] : nullptr, r->p[ip],
-                            tgv ? r->q[ip] : nullptr, params->storage, s);
-            iu = 1 - iu;
-            iw = 1 - iw;
-        }
-        PdArgs pa{};
-        pa.W = lv.W;
-        pa.H = lv.H;
-        pa.pitch = lv.pitch;
-        pa.stride = N0;
-        pa.n = n;
-        pa.tpack = r->tpack;
-        pa.rho = r->rho;
-        pa.flags = r->flags[l];
-        pa.alpha0 = float(params->alpha0);
-        pa.alpha1 = float(params->alpha1);
-        pa.lambda = float(params->lambda);
-        pa.tgv = tgv ? 1 : 0;
-        pa.storage = params->storage;
-        const float* J1l = r->J1 + r->off1[l];
-        for (int wv = 0; wv <= params->warps; ++wv) {
-            // A4 (+A6 of the previous warp): clip, accumulate, linearise
-            const bool last = wv == params->warps;
-            if (last && wv == 0) break;
-            launch_linearise(n, lv.W, lv.H, lv.pitch, N0, j0[l], j0pitch[l], 0, J1l, (long long)r->sj1, r->gamma[l],
-                             r->flags[l], r->u[iu], r->uw, r->w[iw], r->gw, r->tpack, r->rho, wv > 0 ? 1 : 0,
-                             last ? 1 : 0, float(params->du_max), params->storage, s);
-            if (last) break;
-            // A5: K primal-dual iterations (Eq. (11))
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (r->profile && l == 0 && params->iters >= 3) {
-                if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-                    return fail(VFS_E_DEVICE, "hipEventCreate");
-                r->events.emplace_back(e0, e1);
-            }
-            const int np = run_pd(pa, sc, params->iters, r->u, tgv ? r->v : nullptr, r->p, tgv ? r->q : nullptr, iu,
-                                  ip, s, e0, e1);
-            if (e0) r->launches += np;
-        }
-    }
-    // A8: triangulation and outputs
-    launch_triangulate(n, r->geom, l0.W, l0.H, l0.pitch, N0, r->u[iu], r->w[iw], r->flags[0], l0.pitch, u_out, w_out,
-                       depth_out, z_out, valid_out, ip_caller, s);
-    HIP_OK(hipGetLastError());
-    return VFS_OK;
+    return solve_slots(r->ws.slots, n, r->g, *params, s, r);
 }
 
 vfs_status vfs_solve(vfs_rig* rig, const float* I0, const float* I1, size_t pitch_bytes, float* u_out, float* w_out,
@@ -527,6 +509,48 @@ vfs_status vfs_solve(vfs_rig* rig, const float* I0, const float* I1, size_t pitc
 }
 
 // ---------------------------------------------------------------- step entry points
+// Test hooks: each builds a one-pair descriptor over the caller's planes (one
+// level, the caller's pitch), runs the step and waits for it.
+
+namespace {
+
+struct OneSlot {
+    Slot* dev = nullptr;
+    ~OneSlot()
+    {
+        if (dev) (void)hipFree(dev);
+    }
+};
+
+Geometry one_level(int W, int H, size_t pitch)
+{
+    Geometry g{};
+    g.L = 1;
+    g.W[0] = W;
+    g.H[0] = H;
+    g.pitch[0] = int(pitch);
+    g.off[0] = 0;
+    return g;
+}
+
+vfs_status run_one(OneSlot& os, const Slot& sl, hipStream_t s)
+{
+    HIP_OK(hipMalloc(&os.dev, sizeof(Slot)));
+    launch_write_slot(sl, os.dev, s);
+    HIP_OK(hipGetLastError());
+    return VFS_OK;
+}
+
+Launch one_launch(const OneSlot& os, const Geometry& g)
+{
+    Launch lc{};
+    lc.slots = os.dev;
+    lc.n = 1;
+    lc.g = g;
+    return lc;
+}
+
+}  // namespace
 
 vfs_status vfs_step_tensor(int W, int H, size_t pitch, const float* J0, const uint8_t* flags, double beta, double eta,
                            float* tpack, void* hip_stream)
@@ -534,11 +558,19 @@ vfs_status vfs_step_tensor(int W, int H, size_t pitch, const float* J0, const ui
     g_err[0] = 0;
     if (W <= 0 || H <= 0 || pitch < size_t(W) || !J0 || !flags || !tpack || !(beta >= 0.0) || !(eta > 0.0))
         return fail(VFS_E_INVALID, "bad argument");
-    const float* j[1] = {J0};
-    const float b = float(beta), e = float(eta);
-    launch_tensor(1, W, H, j, int(pitch), 0, flags, int(pitch), &b, &e, tpack, int(pitch), 0, ST_F32,
-                  static_cast<hipStream_t>(hip_stream));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Slot sl{};
+    sl.J0 = const_cast<float*>(J0);
+    sl.flags[0] = flags;
+    sl.beta = float(beta);
+    sl.eta = float(eta);
+    sl.tpack = tpack;
+    OneSlot os;
+    vfs_status st = run_one(os, sl, s);
+    if (st) return st;
+    launch_tensor(one_launch(os, one_level(W, H, pitch)), ST_F32, s);
     HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
     return VFS_OK;
 }
 
@@ -550,11 +582,25 @@ vfs_status vfs_step_linearise(int W, int H, size_t pitch, const float* J0, const
     if (W <= 0 || H <= 0 || pitch < size_t(W) || !J0 || !J1 || !gamma || !flags || !u || !u_w || !w || !gamma_w ||
         !tpack || !rho || !(du_max > 0.0))
         return fail(VFS_E_INVALID, "bad argument");
-    const float* j[1] = {J0};
-    launch_linearise(1, W, H, int(pitch), 0, j, int(pitch), 0, J1, 0, reinterpret_cast<const float2*>(gamma), flags, u,
-                     u_w, reinterpret_cast<float2*>(w), reinterpret_cast<float2*>(gamma_w), tpack, rho, clip ? 1 : 0,
-                     clip_only ? 1 : 0, float(du_max), ST_F32, static_cast<hipStream_t>(hip_stream));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Slot sl{};
+    sl.J0 = const_cast<float*>(J0);
+    sl.J1 = const_cast<float*>(J1);
+    sl.gamma[0] = reinterpret_cast<const float2*>(gamma);
+    sl.flags[0] = flags;
+    sl.u[0] = u;
+    sl.uw = u_w;
+    sl.w = reinterpret_cast<float2*>(w);
+    sl.gw = reinterpret_cast<float2*>(gamma_w);
+    sl.tpack = tpack;
+    sl.rho = rho;
+    OneSlot os;
+    vfs_status st = run_one(os, sl, s);
+    if (st) return st;
+    launch_linearise(one_launch(os, one_level(W, H, pitch)), clip ? 1 : 0, clip_only ? 1 : 0, float(du_max), ST_F32,
+                     s);
     HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
     return VFS_OK;
 }
 
@@ -573,23 +619,25 @@ vfs_status vfs_step_pd(int W, int H, size_t pitch, const float* tpack, const flo
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     vfs_params pp = *params;
     pp.iters = iters;
+    pp.storage = VFS_F32;
     const Sched sc = schedule(pp);
-    PdArgs a{};
-    a.W = W; a.H = H; a.pitch = int(pitch); a.stride = 0; a.n = 1;
-    a.tpack = tpack;
-    a.storage = ST_F32;
-    a.rho = rho;
-    a.flags = flags;
-    a.alpha0 = float(params->alpha0);
-    a.alpha1 = float(params->alpha1);
-    a.lambda = float(params->lambda);
-    a.tgv = tgv ? 1 : 0;
-    float* U[2] = {u, su};
-    float2* V[2] = {reinterpret_cast<float2*>(v), reinterpret_cast<float2*>(sv)};
-    void* P[2] = {p, sp};
-    void* Q[2] = {q, sq};
-    int iu = 0, ip = 0;
-    run_pd(a, sc, iters, U, tgv ? V : nullptr, P, tgv ? Q : nullptr, iu, ip, s, nullptr, nullptr);
+    Slot sl{};
+    sl.tpack = const_cast<float*>(tpack);
+    sl.rho = const_cast<float*>(rho);
+    sl.flags[0] = flags;
+    sl.u[0] = u;
+    sl.u[1] = su;
+    sl.v[0] = reinterpret_cast<float2*>(v);
+    sl.v[1] = reinterpret_cast<float2*>(sv);
+    sl.p[0] = p;
+    sl.p[1] = sp;
+    sl.q[0] = q;
+    sl.q[1] = sq;
+    OneSlot os;
+    st = run_one(os, sl, s);
+    if (st) return st;
+    int iu, ip;
+    run_pd(pd_args(one_launch(os, one_level(W, H, pitch)), pp), sc, iters, iu, ip, s, nullptr, nullptr);
     const size_t plane = pitch * size_t(H);
     if (iu) {
         HIP_OK(hipMemcpyAsync(u, su, plane * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -600,6 +648,7 @@ vfs_status vfs_step_pd(int W, int H, size_t pitch, const float* tpack, const flo
         if (tgv) HIP_OK(hipMemcpyAsync(q, sq, plane * sizeof(float4), hipMemcpyDeviceToDevice, s));
     }
     HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
     return VFS_OK;
 }
 
@@ -610,10 +659,39 @@ vfs_status vfs_step_upsample(int Wc, int Hc, size_t pitch_c, const uint8_t* flag
     if (Wc <= 0 || Hc <= 0 || pitch_c < size_t(Wc) || pitch_f < size_t(2 * Wc) || !flags_c || !u_c || !w_c || !u_f ||
         !w_f)
         return fail(VFS_E_INVALID, "bad argument");
-    launch_upsample(1, Wc, Hc, int(pitch_c), 0, flags_c, int(pitch_c), u_c, reinterpret_cast<const float2*>(w_c),
-                    int(pitch_f), 0, u_f, reinterpret_cast<float2*>(w_f), nullptr, nullptr, nullptr, ST_F32,
-                    static_cast<hipStream_t>(hip_stream));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // two-level stack: fine plane (the caller's pitch) then the coarse one
+    Geometry g{};
+    g.L = 2;
+    g.W[0] = 2 * Wc; g.H[0] = 2 * Hc; g.pitch[0] = int(pitch_f); g.off[0] = 0;
+    g.W[1] = Wc; g.H[1] = Hc; g.pitch[1] = int(pitch_c); g.off[1] = (long long)pitch_f * 2 * Hc;
+    const size_t elems = size_t(g.off[1]) + pitch_c * size_t(Hc);
+    struct Bufs {
+        float* u = nullptr;
+        float2* w = nullptr;
+        ~Bufs()
+        {
+            if (u) (void)hipFree(u);
+            if (w) (void)hipFree(w);
+        }
+    } b;
+    HIP_OK(hipMalloc(&b.u, elems * sizeof(float)));
+    HIP_OK(hipMalloc(&b.w, elems * sizeof(float2)));
+    HIP_OK(hipMemcpyAsync(b.u + g.off[1], u_c, pitch_c * Hc * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(b.w + g.off[1], w_c, pitch_c * Hc * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    Slot sl{};
+    sl.flags[1] = flags_c;
+    sl.u[0] = b.u;
+    sl.w = b.w;
+    OneSlot os;
+    vfs_status st = run_one(os, sl, s);
+    if (st) return st;
+    Launch lc = one_launch(os, g);
+    launch_upsample(lc, 0, ST_F32, s);
     HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(u_f, b.u, pitch_f * 2 * Hc * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(w_f, b.w, pitch_f * 2 * Hc * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
     return VFS_OK;
 }
 
@@ -622,16 +700,199 @@ vfs_status vfs_step_triangulate(const vfs_rig* r, size_t pitch, const float* w, 
 {
     g_err[0] = 0;
     if (!r || !w || !depth) return fail(VFS_E_INVALID, "NULL argument");
-    const Level& l0 = r->lv[0];
-    if (pitch < size_t(l0.W)) return fail(VFS_E_INVALID, "pitch too small");
-    // reads u only to copy it to u_out, which is not requested here
-    float* dz[1] = {depth};
-    float* zz[1] = {z};
-    uint8_t* vv[1] = {valid};
-    launch_triangulate(1, r->geom, l0.W, l0.H, int(pitch), 0, nullptr, reinterpret_cast<const float2*>(w),
-                       r->flags[0], l0.pitch, nullptr, nullptr, dz, z ? zz : nullptr, valid ? vv : nullptr,
-                       int(pitch), static_cast<hipStream_t>(hip_stream));
+    const int W = r->g.W[0], H = r->g.H[0], rp = r->g.pitch[0];
+    if (pitch < size_t(W)) return fail(VFS_E_INVALID, "pitch too small");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    float2* ww = nullptr;
+    HIP_OK(hipMalloc(&ww, size_t(rp) * H * sizeof(float2)));
+    struct Free {
+        void* p;
+        ~Free() { (void)hipFree(p); }
+    } fw{ww};
+    HIP_OK(hipMemcpy2DAsync(ww, rp * sizeof(float2), w, pitch * sizeof(float2), W * sizeof(float2), H,
+                            hipMemcpyDeviceToDevice, s));
+    Slot sl{};
+    bind_rig(sl, r);
+    sl.w = ww;
+    sl.out_pitch = int(pitch);
+    sl.depth_out = depth;
+    sl.z_out = z;
+    sl.valid_out = valid;
+    OneSlot os;
+    vfs_status st = run_one(os, sl, s);
+    if (st) return st;
+    launch_triangulate(one_launch(os, r->g), s);
     HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+    return VFS_OK;
+}
+
+// ---------------------------------------------------------------- energy and difference statistics
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+EnergyConsts energy_consts(const vfs_params& p)
+{
+    EnergyConsts k{};
+    k.lambda = float(p.lambda);
+    k.alpha0 = float(p.alpha0);
+    k.alpha1 = float(p.alpha1);
+    k.tgv = p.reg == VFS_TGV ? 1 : 0;
+    k.storage = ST_F32;
+    return k;
+}
+
+}  // namespace
+
+vfs_status vfs_step_energy(int W, int H, size_t pitch, const float* tpack, const float* rho, const uint8_t* flags,
+                           const float* u, const float* v, const vfs_params* params, double* energy,
+                           void* hip_stream)
+{
+    g_err[0] = 0;
+    vfs_status st = check_params(params);
+    if (st) return st;
+    const bool tgv = params->reg == VFS_TGV;
+    if (W <= 0 || H <= 0 || pitch < size_t(W) || !tpack || !rho || !flags || !u || (tgv && !v) || !energy)
+        return fail(VFS_E_INVALID, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Slot sl{};
+    sl.tpack = const_cast<float*>(tpack);
+    sl.rho = const_cast<float*>(rho);
+    sl.flags[0] = flags;
+    sl.u[0] = const_cast<float*>(u);
+    sl.v[0] = reinterpret_cast<float2*>(const_cast<float*>(v));
+    OneSlot os;
+    st = run_one(os, sl, s);
+    if (st) return st;
+    Launch lc = one_launch(os, one_level(W, H, pitch));
+    DevBuf part;
+    HIP_OK(hipMalloc(&part.p, (energy_partials(lc) + 1) * sizeof(double)));
+    double* d = static_cast<double*>(part.p);
+    launch_energy(lc, energy_consts(*params), d + 1, d, s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(energy, d, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return VFS_OK;
+}
+
+vfs_status vfs_step_pd_energy(int W, int H, size_t pitch, const float* tpack, const float* rho, const uint8_t* flags,
+                              float* u, float* v, float* p, float* q, float* su, float* sv, float* sp, float* sq,
+                              const vfs_params* params, int iters, double* energy, void* hip_stream)
+{
+    g_err[0] = 0;
+    vfs_status st = check_params(params);
+    if (st) return st;
+    const bool tgv = params->reg == VFS_TGV;
+    if (W <= 0 || H <= 0 || pitch < size_t(W) || !tpack || !rho || !flags || !u || !p || !su || !sp || iters < 1 ||
+        !energy || (tgv && (!v || !q || !sv || !sq)))
+        return fail(VFS_E_INVALID, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    vfs_params pp = *params;
+    pp.iters = iters;
+    pp.storage = VFS_F32;
+    const Sched sc = schedule(pp);
+    Slot sl{};
+    sl.tpack = const_cast<float*>(tpack);
+    sl.rho = const_cast<float*>(rho);
+    sl.flags[0] = flags;
+    sl.u[0] = u;
+    sl.u[1] = su;
+    sl.v[0] = reinterpret_cast<float2*>(v);
+    sl.v[1] = reinterpret_cast<float2*>(sv);
+    sl.p[0] = p;
+    sl.p[1] = sp;
+    sl.q[0] = q;
+    sl.q[1] = sq;
+    OneSlot os;
+    st = run_one(os, sl, s);
+    if (st) return st;
+    Launch lc = one_launch(os, one_level(W, H, pitch));
+    const size_t np = energy_partials(lc);
+    DevBuf buf;
+    HIP_OK(hipMalloc(&buf.p, (np + iters + 1) * sizeof(double)));
+    double* e = static_cast<double*>(buf.p);
+    double* part = e + iters + 1;
+    const EnergyConsts ek = energy_consts(pp);
+    // the energy of x^0, then one iteration per launch with the energy of
+    // each new primal iterate x^k (the memory holds (x^k, y^{k+1}) between
+    // launches)
+    int iu = 0, ip = 0;
+    auto energy_at = [&](int k) {
+        lc.iu = iu;
+        launch_energy(lc, ek, part, e + k, s);
+    };
+    energy_at(0);
+    PdArgs a = pd_args(lc, pp);
+    a.mode = PD_DUAL_FIRST;
+    a.tau_scale = 1.f;
+    a.sigma_scale = 1.f / sc.s[0];
+    a.theta = 1.f;
+    a.lc.iu = iu;
+    a.lc.ip = ip;
+    launch_pd(a, s);
+    ip ^= 1;
+    for (int k = 1; k < iters; ++k) {
+        a.mode = PD_FUSED;
+        a.tau_scale = sc.s[k - 1];
+        a.theta = sc.theta[k - 1];
+        a.sigma_scale = 1.f / sc.s[k];
+        a.lc.iu = iu;
+        a.lc.ip = ip;
+        launch_pd(a, s);
+        iu ^= 1;
+        ip ^= 1;
+        energy_at(k);
+    }
+    a.mode = PD_PRIMAL_LAST;
+    a.tau_scale = sc.s[iters - 1];
+    a.sigma_scale = 1.f;
+    a.theta = 1.f;
+    a.lc.iu = iu;
+    a.lc.ip = ip;
+    launch_pd(a, s);
+    iu ^= 1;
+    energy_at(iters);
+    HIP_OK(hipGetLastError());
+    const size_t plane = pitch * size_t(H);
+    if (iu) {
+        HIP_OK(hipMemcpyAsync(u, su, plane * sizeof(float), hipMemcpyDeviceToDevice, s));
+        if (tgv) HIP_OK(hipMemcpyAsync(v, sv, plane * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    }
+    if (ip) {
+        HIP_OK(hipMemcpyAsync(p, sp, plane * sizeof(float2), hipMemcpyDeviceToDevice, s));
+        if (tgv) HIP_OK(hipMemcpyAsync(q, sq, plane * sizeof(float4), hipMemcpyDeviceToDevice, s));
+    }
+    HIP_OK(hipMemcpyAsync(energy, e, (iters + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return VFS_OK;
+}
+
+vfs_status vfs_diff_stats(int W, int H, size_t pitch, const float* a, const float* b, const uint8_t* flags,
+                          double* mean_abs, double* max_abs, long long* count, void* hip_stream)
+{
+    g_err[0] = 0;
+    if (W <= 0 || H <= 0 || pitch < size_t(W) || !a || !b) return fail(VFS_E_INVALID, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t n = diff_partials(W, H);
+    DevBuf buf;
+    HIP_OK(hipMalloc(&buf.p, (3 * n + 3) * sizeof(double)));
+    double* out = static_cast<double*>(buf.p);
+    launch_diff_stats(W, H, int(pitch), a, b, flags, out + 3, out, s);
+    HIP_OK(hipGetLastError());
+    double h[3];
+    HIP_OK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (count) *count = (long long)h[2];
+    if (mean_abs) *mean_abs = h[2] > 0 ? h[0] / h[2] : 0.0;
+    if (max_abs) *max_abs = h[1];
     return VFS_OK;
 }
 

@@ -63,127 +63,155 @@ __device__ inline float2 bicubic2(const float2* g, int pitch, int W, int H, int 
     return make_float2(sx, sy);
 }
 
-__global__ void prerotate_kernel(PairPtrs I1, int W, int H, const float2* calib, int cpitch, float* out,
-                                 int opitch, long long ostride)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y, b = blockIdx.z;
-    if (j >= W) return;
-    const float2 c = calib[(size_t)i * cpitch + j];
-    out[b * ostride + (size_t)i * opitch + j] = bilinear(I1.in[b], I1.in_pitch, W, H, j, i, c.x, c.y);
-}
-
-struct FinePtrs { const float* p[kMaxBatch]; };
-
-__global__ void downsample_kernel(int Wc, int Hc, FinePtrs fine, int fpitch, long long fstride, float* coarse,
-                                  int cpitch, long long cstride)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y, b = blockIdx.z;
-    if (j >= Wc) return;
-    const float* f = fine.p[b] + (fstride ? b * fstride : 0);
-    const float* r0 = f + (size_t)(2 * i) * fpitch + 2 * j;
-    const float* r1 = r0 + fpitch;
-    coarse[b * cstride + (size_t)i * cpitch + j] = 0.25f * (r0[0] + r0[1] + r1[0] + r1[1]);
-}
-
 __device__ inline bool in_mask(const uint8_t* flags, int fpitch, int W, int H, int i, int j)
 {
     return i >= 0 && i < H && j >= 0 && j < W && (flags[(size_t)i * fpitch + j] & F_MASK);
 }
 
-struct Params2 { float beta[kMaxBatch]; float eta[kMaxBatch]; };
+// Pixel (j, i) of pair z handled by this thread at the pair's level pk.l;
+// false if the pair is not in the launch or the pixel lies outside its level.
+__device__ inline bool pixel_of(const Launch& lc, Pick& pk, int& j, int& i)
+{
+    if (!pick(lc, blockIdx.z, pk)) return false;
+    j = blockIdx.x * blockDim.x + threadIdx.x;
+    i = blockIdx.y;
+    return j < lc.g.W[pk.l] && i < lc.g.H[pk.l];
+}
+
+__device__ inline int par_u(const Launch& lc, const Pick& pk) { return (lc.iu ^ int(pk.flip)) & 1; }
+__device__ inline int par_p(const Launch& lc, const Pick& pk) { return (lc.ip ^ int(pk.flip >> 1)) & 1; }
+
+// Level 0 of both pyramids: J1 = I1 pre-rotated (Sec. IV-A), J0 = I0.
+__global__ void prerotate_kernel(Launch lc)
+{
+    Pick pk;
+    int j, i;
+    if (!pixel_of(lc, pk, j, i)) return;
+    const Slot& sl = lc.slots[blockIdx.z];
+    const int W = lc.g.W[0], H = lc.g.H[0], pitch = lc.g.pitch[0];
+    const size_t o = (size_t)i * pitch + j;
+    const float2 c = sl.calib[o];
+    sl.J1[o] = bilinear(sl.I1, sl.in_pitch, W, H, j, i, c.x, c.y);
+    sl.J0[o] = sl.I0[(size_t)i * sl.in_pitch + j];
+}
+
+// Level l of both pyramids from level l - 1 (2x2 box filter).
+__global__ void downsample_kernel(Launch lc)
+{
+    Pick pk;
+    int j, i;
+    if (!pixel_of(lc, pk, j, i)) return;
+    const Slot& sl = lc.slots[blockIdx.z];
+    const int l = pk.l;
+    const int fp = lc.g.pitch[l - 1];
+    const size_t fo = lc.g.off[l - 1] + (size_t)(2 * i) * fp + 2 * j;
+    const size_t co = lc.g.off[l] + (size_t)i * lc.g.pitch[l] + j;
+    const float* a = sl.J0 + fo;
+    const float* b = sl.J1 + fo;
+    sl.J0[co] = 0.25f * (a[0] + a[1] + a[fp] + a[fp + 1]);
+    sl.J1[co] = 0.25f * (b[0] + b[1] + b[fp] + b[fp + 1]);
+}
 
 template <int S>
-__global__ void tensor_kernel(int W, int H, FinePtrs J0, int jpitch, long long jstride, const uint8_t* flags,
-                              int fpitch, Params2 be, void* tpack, int tpitch, long long tstride)
+__global__ void tensor_kernel(Launch lc)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y, b = blockIdx.z;
-    if (j >= W) return;
+    Pick pk;
+    int j, i;
+    if (!pixel_of(lc, pk, j, i)) return;
+    const Slot& sl = lc.slots[blockIdx.z];
+    const int l = pk.l, W = lc.g.W[l], H = lc.g.H[l], pitch = lc.g.pitch[l];
+    const uint8_t* flags = sl.flags[l];
     float4 t = make_float4(1.f, 0.f, 1.f, 0.f);
-    if (in_mask(flags, fpitch, W, H, i, j)) {
-        const float* J = J0.p[b] + (jstride ? b * jstride : 0);
-        const float* r = J + (size_t)i * jpitch;
+    if (in_mask(flags, pitch, W, H, i, j)) {
+        const float* r = sl.J0 + lc.g.off[l] + (size_t)i * pitch;
         const float c = r[j];
         float gx = 0.f, gy = 0.f;
-        const bool l = in_mask(flags, fpitch, W, H, i, j - 1), rr = in_mask(flags, fpitch, W, H, i, j + 1);
-        if (l && rr) gx = 0.5f * (r[j + 1] - r[j - 1]);
-        else if (rr) gx = r[j + 1] - c;
-        else if (l) gx = c - r[j - 1];
-        const bool u = in_mask(flags, fpitch, W, H, i - 1, j), d = in_mask(flags, fpitch, W, H, i + 1, j);
-        if (u && d) gy = 0.5f * (r[j + jpitch] - r[j - jpitch]);
-        else if (d) gy = r[j + jpitch] - c;
-        else if (u) gy = c - r[j - jpitch];
+        const bool lf = in_mask(flags, pitch, W, H, i, j - 1), rt = in_mask(flags, pitch, W, H, i, j + 1);
+        if (lf && rt) gx = 0.5f * (r[j + 1] - r[j - 1]);
+        else if (rt) gx = r[j + 1] - c;
+        else if (lf) gx = c - r[j - 1];
+        const bool up = in_mask(flags, pitch, W, H, i - 1, j), dn = in_mask(flags, pitch, W, H, i + 1, j);
+        if (up && dn) gy = 0.5f * (r[j + pitch] - r[j - pitch]);
+        else if (dn) gy = r[j + pitch] - c;
+        else if (up) gy = c - r[j - pitch];
         const float g = sqrtf(gx * gx + gy * gy);
         if (!(g < 1e-12f)) {
             const float nx = gx / g, ny = gy / g;
-            const float e = expf(-be.beta[b] * powf(g, be.eta[b]));
+            const float e = expf(-sl.beta * powf(g, sl.eta));
             t = make_float4(e * nx * nx + ny * ny, (e - 1.f) * nx * ny, e * ny * ny + nx * nx, 0.f);
         }
     }
-    st4<S>(tpack, b * tstride + (size_t)i * tpitch + j, t);
+    st4<S>(sl.tpack, (size_t)i * pitch + j, t);
 }
 
+// clip < 0: clip when the slot's warp index is > 0 (serving ticks).
 template <int S>
-__global__ void linearise_kernel(int W, int H, int pitch, long long stride, FinePtrs J0, int j0pitch,
-                                 long long j0stride, const float* J1, long long j1stride, const float2* gamma,
-                                 const uint8_t* flags, float* u, float* u_w, float2* w, float2* gamma_w,
-                                 void* tpack, float* rho, int clip, int clip_only, float du_max)
+__global__ void linearise_kernel(Launch lc, int clip, int clip_only, float du_max)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y, b = blockIdx.z;
-    if (j >= W) return;
-    const size_t o = b * stride + (size_t)i * pitch + j;
-    float uu = u[o];
-    float2 ww = w[o];
-    if (clip) {
+    Pick pk;
+    int j, i;
+    if (!pixel_of(lc, pk, j, i)) return;
+    const Slot& sl = lc.slots[blockIdx.z];
+    const int l = pk.l, W = lc.g.W[l], H = lc.g.H[l], pitch = lc.g.pitch[l];
+    const long long off = lc.g.off[l];
+    const size_t o = (size_t)i * pitch + j;       // single-level planes
+    const size_t os = off + o;                    // level-stacked planes
+    float* u = sl.u[par_u(lc, pk)];
+    const bool do_clip = clip < 0 ? pk.warp > 0 : clip != 0;
+    float uu = u[os];
+    float2 ww = sl.w[os];
+    if (do_clip) {
         // Sec. III-C / Algorithm 1: clip the increment of the finished warp, accumulate
-        float du = uu - u_w[o];
+        float du = uu - sl.uw[o];
         du = fminf(fmaxf(du, -du_max), du_max);
-        uu = u_w[o] + du;
-        const float2 gw = gamma_w[o];
+        uu = sl.uw[o] + du;
+        const float2 gw = sl.gw[o];
         ww.x += du * gw.x;
         ww.y += du * gw.y;
-        u[o] = uu;
-        w[o] = ww;
+        u[os] = uu;
+        sl.w[os] = ww;
     }
     if (clip_only) return;
-    u_w[o] = uu;
+    sl.uw[o] = uu;
     // tangent at the warped point (bicubic sample of the trajectory field, renormalised)
-    float2 g = bicubic2(gamma, pitch, W, H, j, i, ww.x, ww.y);
+    float2 g = bicubic2(sl.gamma[l], pitch, W, H, j, i, ww.x, ww.y);
     const float n = sqrtf(g.x * g.x + g.y * g.y);
     if (n > 0.f) { g.x /= n; g.y /= n; } else { g.x = 0.f; g.y = 0.f; }
-    gamma_w[o] = g;
+    sl.gw[o] = g;
     float Iu = 0.f, rc = 0.f;
-    if (flags[(size_t)i * pitch + j] & F_DATA) {
-        const float* J1b = J1 + b * j1stride;
-        const float i1 = bilinear(J1b, pitch, W, H, j, i, ww.x, ww.y);
-        const float i1s = bilinear(J1b, pitch, W, H, j, i, ww.x + g.x, ww.y + g.y);
-        const float* J0b = J0.p[b] + (j0stride ? b * j0stride : 0);
+    if (sl.flags[l][o] & F_DATA) {
+        const float* J1 = sl.J1 + off;
+        const float i1 = bilinear(J1, pitch, W, H, j, i, ww.x, ww.y);
+        const float i1s = bilinear(J1, pitch, W, H, j, i, ww.x + g.x, ww.y + g.y);
         // rho_c is formed from I_u as stored, so that rho_c + u I_u is exact at u = u_w
         Iu = as_stored<S>(i1s - i1);
-        rc = i1 - J0b[(size_t)i * j0pitch + j] - uu * Iu;
+        rc = i1 - sl.J0[os] - uu * Iu;
     }
     if constexpr (S == ST_F32) {
-        static_cast<float4*>(tpack)[o].w = Iu;
+        static_cast<float4*>(sl.tpack)[o].w = Iu;
     } else {
-        float4 t = ld4<S>(tpack, o);
+        float4 t = ld4<S>(sl.tpack, o);
         t.w = Iu;
-        st4<S>(tpack, o, t);
+        st4<S>(sl.tpack, o, t);
     }
-    rho[o] = rc;
+    sl.rho[o] = rc;
 }
 
+// Level l + 1 -> level l (Sec. IV-B): u doubled, w doubled (bilinear over the
+// coarse mask); v, p, q restart at zero.  Same parity in and out.
 template <int S>
-__global__ void upsample_kernel(int Wc, int Hc, int cpitch, long long cstride, const uint8_t* flags_c, int fcpitch,
-                                const float* u_c, const float2* w_c, int fpitch, long long fstride, float* u_f,
-                                float2* w_f, float2* v_f, void* p_f, void* q_f)
+__global__ void upsample_kernel(Launch lc, int tgv)
 {
-    const int Wf = 2 * Wc;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y, b = blockIdx.z;
-    if (j >= Wf) return;
+    Pick pk;
+    int j, i;
+    if (!pixel_of(lc, pk, j, i)) return;
+    const Slot& sl = lc.slots[blockIdx.z];
+    const int l = pk.l, lc1 = l + 1;
+    const int Wc = lc.g.W[lc1], Hc = lc.g.H[lc1], cp = lc.g.pitch[lc1];
+    const uint8_t* flags_c = sl.flags[lc1];
+    const int pu = par_u(lc, pk), pp = par_p(lc, pk);
+    const float* u_c = sl.u[pu] + lc.g.off[lc1];
+    const float2* w_c = sl.w + lc.g.off[lc1];
     const float x = 0.5f * j - 0.25f, y = 0.5f * i - 0.25f;
     const float fx0 = floorf(x), fy0 = floorf(y), ax = x - fx0, ay = y - fy0;
     const int x0 = int(fx0), y0 = int(fy0);
@@ -193,64 +221,62 @@ __global__ void upsample_kernel(int Wc, int Hc, int cpitch, long long cstride, c
         const float wy = bb ? ay : 1.f - ay;
         for (int aa = 0; aa < 2; ++aa) {
             const int xx = clampi(x0 + aa, 0, Wc - 1);
-            if (!(flags_c[(size_t)yy * fcpitch + xx] & F_MASK)) continue;
+            const size_t co = (size_t)yy * cp + xx;
+            if (!(flags_c[co] & F_MASK)) continue;
             const float wt = (aa ? ax : 1.f - ax) * wy;
-            const size_t co = b * cstride + (size_t)yy * cpitch + xx;
             sw += wt;
             su += wt * u_c[co];
             s1 += wt * w_c[co].x;
             s2 += wt * w_c[co].y;
         }
     }
-    const size_t fo = b * fstride + (size_t)i * fpitch + j;
+    const size_t fo = lc.g.off[l] + (size_t)i * lc.g.pitch[l] + j;
     if (sw > 0.f) {
-        u_f[fo] = 2.f * su / sw;
-        w_f[fo] = make_float2(2.f * s1 / sw, 2.f * s2 / sw);
+        sl.u[pu][fo] = 2.f * su / sw;
+        sl.w[fo] = make_float2(2.f * s1 / sw, 2.f * s2 / sw);
     } else {
-        u_f[fo] = 0.f;
-        w_f[fo] = make_float2(0.f, 0.f);
+        sl.u[pu][fo] = 0.f;
+        sl.w[fo] = make_float2(0.f, 0.f);
     }
-    if (v_f) v_f[fo] = make_float2(0.f, 0.f);
-    if (p_f) st2<S>(p_f, fo, make_float2(0.f, 0.f));
-    if (q_f) st4<S>(q_f, fo, make_float4(0.f, 0.f, 0.f, 0.f));
+    if (sl.p[pp]) st2<S>(sl.p[pp], fo, make_float2(0.f, 0.f));
+    if (tgv) {
+        sl.v[pu][fo] = make_float2(0.f, 0.f);
+        st4<S>(sl.q[pp], fo, make_float4(0.f, 0.f, 0.f, 0.f));
+    }
 }
 
 template <int S>
-__global__ void zero_state_kernel(int W, int pitch, long long stride, float* u, float2* w, float2* v, void* p,
-                                  void* q)
+__global__ void zero_state_kernel(Launch lc, int tgv)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y, b = blockIdx.z;
-    if (j >= W) return;
-    const size_t o = b * stride + (size_t)i * pitch + j;
-    u[o] = 0.f;
-    w[o] = make_float2(0.f, 0.f);
-    if (v) v[o] = make_float2(0.f, 0.f);
-    st2<S>(p, o, make_float2(0.f, 0.f));
-    if (q) st4<S>(q, o, make_float4(0.f, 0.f, 0.f, 0.f));
+    Pick pk;
+    int j, i;
+    if (!pixel_of(lc, pk, j, i)) return;
+    const Slot& sl = lc.slots[blockIdx.z];
+    const int pu = par_u(lc, pk), pp = par_p(lc, pk);
+    const size_t o = lc.g.off[pk.l] + (size_t)i * lc.g.pitch[pk.l] + j;
+    sl.u[pu][o] = 0.f;
+    sl.w[o] = make_float2(0.f, 0.f);
+    st2<S>(sl.p[pp], o, make_float2(0.f, 0.f));
+    if (tgv) {
+        sl.v[pu][o] = make_float2(0.f, 0.f);
+        st4<S>(sl.q[pp], o, make_float4(0.f, 0.f, 0.f, 0.f));
+    }
 }
 
-struct OutPtrs {
-    float* u[kMaxBatch];
-    float* w[kMaxBatch];
-    float* depth[kMaxBatch];
-    float* z[kMaxBatch];
-    uint8_t* valid[kMaxBatch];
-};
-
 // Closest approach of the rays a = pi0^-1(x) from the origin and
-// b = pi0^-1(x + w) from C = -t', in double precision.
-__global__ void triangulate_kernel(RigGeom g, int W, int H, int pitch, long long stride, const float* u,
-                                   const float2* w, const uint8_t* flags, int fpitch, OutPtrs out, int opitch)
+// b = pi0^-1(x + w) from C = -t', in double precision (level 0).
+__global__ void triangulate_kernel(Launch lc)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y, b = blockIdx.z;
-    if (j >= W) return;
-    const size_t o = b * stride + (size_t)i * pitch + j;
-    const size_t oo = (size_t)i * opitch + j;
-    const float2 ww = w[o];
-    if (out.u[b]) out.u[b][oo] = u[o];
-    if (out.w[b]) { out.w[b][2 * oo] = ww.x; out.w[b][2 * oo + 1] = ww.y; }
+    Pick pk;
+    int j, i;
+    if (!pixel_of(lc, pk, j, i)) return;
+    const Slot& sl = lc.slots[blockIdx.z];
+    const RigGeom& g = *sl.geom;
+    const size_t o = (size_t)i * lc.g.pitch[0] + j;
+    const size_t oo = (size_t)i * sl.out_pitch + j;
+    const float2 ww = sl.w[o];
+    if (sl.u_out) sl.u_out[oo] = sl.u[par_u(lc, pk)][o];
+    if (sl.w_out) { sl.w_out[2 * oo] = ww.x; sl.w_out[2 * oo + 1] = ww.y; }
     double a[3], bb[3];
     cam_ray(g.cam0, j, i, a);
     cam_ray(g.cam0, double(j) + double(ww.x), double(i) + double(ww.y), bb);
@@ -260,7 +286,7 @@ __global__ void triangulate_kernel(RigGeom g, int W, int H, int pitch, long long
     const double den = 1.0 - ab * ab;
     float depth = __builtin_inff(), z = __builtin_inff();
     uint8_t ok = 0;
-    if (den > 1e-12 && (flags[(size_t)i * fpitch + j] & F_DATA)) {
+    if (den > 1e-12 && (sl.flags[0][o] & F_DATA)) {
         const double d0 = (aC - ab * bC) / den, d1 = (ab * aC - bC) / den;
         if (d0 > 0.0 && d1 > 0.0) {
             depth = float(d0);
@@ -268,29 +294,45 @@ __global__ void triangulate_kernel(RigGeom g, int W, int H, int pitch, long long
             ok = 1;
         }
     }
-    if (out.depth[b]) out.depth[b][oo] = depth;
-    if (out.z[b]) out.z[b][oo] = z;
-    if (out.valid[b]) out.valid[b][oo] = ok;
+    if (sl.depth_out) sl.depth_out[oo] = depth;
+    if (sl.z_out) sl.z_out[oo] = z;
+    if (sl.valid_out) sl.valid_out[oo] = ok;
 }
 
-inline dim3 grid_for(int W, int H, int n) { return dim3((W + 63) / 64, H, n); }
+// Descriptor writes: one thread, every store a vector-memory store.
+__global__ void write_slot_kernel(Slot sl, Slot* dst)
+{
+    if (threadIdx.x == 0) *dst = sl;
+}
+
+__global__ void write_ctrl_kernel(CtrlBlock cb, int n, Ctrl* dst)
+{
+    const int z = threadIdx.x;
+    if (z < n) dst[z] = cb.c[z];
+}
+
+inline dim3 grid_for(const Launch& lc) { return dim3((lc.g.W[lc.gl] + 63) / 64, lc.g.H[lc.gl], lc.n); }
 
 }  // namespace
 
-void launch_prerotate(const PairPtrs& I1, int n, int W, int H, const float2* calib, int cpitch, float* out,
-                      int opitch, long long ostride, hipStream_t s)
+void launch_write_slot(const Slot& sl, Slot* dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(prerotate_kernel, grid_for(W, H, n), dim3(64), 0, s, I1, W, H, calib, cpitch, out, opitch,
-                       ostride);
+    hipLaunchKernelGGL(write_slot_kernel, dim3(1), dim3(64), 0, s, sl, dst);
 }
 
-void launch_downsample(int n, int Wc, int Hc, const float* const* fine, int fpitch, long long fstride, float* coarse,
-                       int cpitch, long long cstride, hipStream_t s)
+void launch_write_ctrl(const CtrlBlock& cb, int n, Ctrl* dst, hipStream_t s)
 {
-    FinePtrs f;
-    for (int b = 0; b < n; ++b) f.p[b] = fine[b];
-    hipLaunchKernelGGL(downsample_kernel, grid_for(Wc, Hc, n), dim3(64), 0, s, Wc, Hc, f, fpitch, fstride, coarse,
-                       cpitch, cstride);
+    hipLaunchKernelGGL(write_ctrl_kernel, dim3(1), dim3(kMaxBatch), 0, s, cb, n, dst);
+}
+
+void launch_prerotate(const Launch& lc, hipStream_t s)
+{
+    hipLaunchKernelGGL(prerotate_kernel, grid_for(lc), dim3(64), 0, s, lc);
+}
+
+void launch_downsample(const Launch& lc, hipStream_t s)
+{
+    hipLaunchKernelGGL(downsample_kernel, grid_for(lc), dim3(64), 0, s, lc);
 }
 
 #define VFS_BY_STORAGE(storage, call)                   \
@@ -300,64 +342,30 @@ void launch_downsample(int n, int Wc, int Hc, const float* const* fine, int fpit
         else { constexpr int S = ST_F32; call; }                             \
     } while (0)
 
-void launch_tensor(int n, int W, int H, const float* const* J0, int jpitch, long long jstride, const uint8_t* flags,
-                   int fpitch, const float* betas, const float* etas, void* tpack, int tpitch, long long tstride,
-                   int storage, hipStream_t s)
+void launch_tensor(const Launch& lc, int storage, hipStream_t s)
 {
-    FinePtrs f;
-    Params2 be;
-    for (int b = 0; b < n; ++b) {
-        f.p[b] = J0[b];
-        be.beta[b] = betas[b];
-        be.eta[b] = etas[b];
-    }
-    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(tensor_kernel<S>, grid_for(W, H, n), dim3(64), 0, s, W, H, f, jpitch,
-                                               jstride, flags, fpitch, be, tpack, tpitch, tstride));
+    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(tensor_kernel<S>, grid_for(lc), dim3(64), 0, s, lc));
 }
 
-void launch_linearise(int n, int W, int H, int pitch, long long stride, const float* const* J0, int j0pitch,
-                      long long j0stride, const float* J1, long long j1stride, const float2* gamma,
-                      const uint8_t* flags, float* u, float* u_w, float2* w, float2* gamma_w, void* tpack,
-                      float* rho, int clip, int clip_only, float du_max, int storage, hipStream_t s)
+void launch_linearise(const Launch& lc, int clip, int clip_only, float du_max, int storage, hipStream_t s)
 {
-    FinePtrs f;
-    for (int b = 0; b < n; ++b) f.p[b] = J0[b];
-    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(linearise_kernel<S>, grid_for(W, H, n), dim3(64), 0, s, W, H, pitch,
-                                               stride, f, j0pitch, j0stride, J1, j1stride, gamma, flags, u, u_w, w,
-                                               gamma_w, tpack, rho, clip, clip_only, du_max));
+    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(linearise_kernel<S>, grid_for(lc), dim3(64), 0, s, lc, clip,
+                                               clip_only, du_max));
 }
 
-void launch_upsample(int n, int Wc, int Hc, int cpitch, long long cstride, const uint8_t* flags_c, int fcpitch,
-                     const float* u_c, const float2* w_c, int fpitch, long long fstride, float* u_f, float2* w_f,
-                     float2* v_f, void* p_f, void* q_f, int storage, hipStream_t s)
+void launch_upsample(const Launch& lc, int tgv, int storage, hipStream_t s)
 {
-    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(upsample_kernel<S>, grid_for(2 * Wc, 2 * Hc, n), dim3(64), 0, s, Wc,
-                                               Hc, cpitch, cstride, flags_c, fcpitch, u_c, w_c, fpitch, fstride, u_f,
-                                               w_f, v_f, p_f, q_f));
+    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(upsample_kernel<S>, grid_for(lc), dim3(64), 0, s, lc, tgv));
 }
 
-void launch_zero_state(int n, int W, int H, int pitch, long long stride, float* u, float2* w, float2* v, void* p,
-                       void* q, int storage, hipStream_t s)
+void launch_zero_state(const Launch& lc, int tgv, int storage, hipStream_t s)
 {
-    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(zero_state_kernel<S>, grid_for(W, H, n), dim3(64), 0, s, W, pitch,
-                                               stride, u, w, v, p, q));
+    VFS_BY_STORAGE(storage, hipLaunchKernelGGL(zero_state_kernel<S>, grid_for(lc), dim3(64), 0, s, lc, tgv));
 }
 
-void launch_triangulate(int n, const RigGeom& g, int W, int H, int pitch, long long stride, const float* u,
-                        const float2* w, const uint8_t* flags, int fpitch, float* const* u_out, float* const* w_out,
-                        float* const* depth_out, float* const* z_out, uint8_t* const* valid_out, int opitch,
-                        hipStream_t s)
+void launch_triangulate(const Launch& lc, hipStream_t s)
 {
-    OutPtrs o;
-    for (int b = 0; b < n; ++b) {
-        o.u[b] = u_out ? u_out[b] : nullptr;
-        o.w[b] = w_out ? w_out[b] : nullptr;
-        o.depth[b] = depth_out ? depth_out[b] : nullptr;
-        o.z[b] = z_out ? z_out[b] : nullptr;
-        o.valid[b] = valid_out ? valid_out[b] : nullptr;
-    }
-    hipLaunchKernelGGL(triangulate_kernel, grid_for(W, H, n), dim3(64), 0, s, g, W, H, pitch, stride, u, w, flags,
-                       fpitch, o, opitch);
+    hipLaunchKernelGGL(triangulate_kernel, grid_for(lc), dim3(64), 0, s, lc);
 }
 
 }  // namespace vfs

@@ -19,6 +19,10 @@
 // Storage: p, q and the tensor pack are read and written as FP32, FP16 or
 // BF16 (template S); u, v, rho_c and all arithmetic are FP32.
 //
+// Every launch reads each pair's planes from its slot descriptor; in serving
+// ticks the pairs of one launch may be at different levels (the grid covers
+// the largest, workgroups beyond a pair's level exit at once).
+//
 // Work decomposition: one 64-lane wavefront owns a strip of columns (62 for
 // the one-iteration modes: lanes 1..62, lanes 0 and 63 are the x-halo; 60 for
 // PD_FUSED2: lanes 2..61) and marches down 16 rows plus a halo above and
@@ -87,20 +91,64 @@ __device__ inline Row zero_row()
     return w;
 }
 
+// One pair's planes at the level of a launch (workgroup-uniform).  State
+// pointers already include the level's offset in the level-stacked arrays.
+struct Planes {
+    int W, H, pitch;
+    const float* u_in;
+    float* u_out;
+    const float2* v_in;
+    float2* v_out;
+    const void* p_in;
+    void* p_out;
+    const void* q_in;
+    void* q_out;
+    const void* tpack;          // single-level
+    const float* rho;           // single-level
+    const uint8_t* flags;
+};
+
+template <int S>
+__device__ inline bool planes_of(const PdArgs& a, int z, Planes& P)
+{
+    Pick pk;
+    if (!pick(a.lc, z, pk)) return false;
+    const Slot& sl = a.lc.slots[z];
+    const int l = pk.l;
+    const long long off = a.lc.g.off[l];
+    const int pu = (a.lc.iu ^ int(pk.flip)) & 1, pp = (a.lc.ip ^ int(pk.flip >> 1)) & 1;
+    constexpr long long E2 = S == ST_F32 ? 8 : 4, E4 = S == ST_F32 ? 16 : 8;
+    P.W = a.lc.g.W[l];
+    P.H = a.lc.g.H[l];
+    P.pitch = a.lc.g.pitch[l];
+    P.u_in = sl.u[pu] + off;
+    P.u_out = sl.u[pu ^ 1] + off;
+    P.v_in = sl.v[pu] + off;
+    P.v_out = sl.v[pu ^ 1] + off;
+    P.p_in = static_cast<const char*>(sl.p[pp]) + off * E2;
+    P.p_out = static_cast<char*>(sl.p[pp ^ 1]) + off * E2;
+    P.q_in = static_cast<const char*>(sl.q[pp]) + off * E4;
+    P.q_out = static_cast<char*>(sl.q[pp ^ 1]) + off * E4;
+    P.tpack = sl.tpack;
+    P.rho = sl.rho;
+    P.flags = sl.flags[l];
+    return true;
+}
+
 template <bool TGV, bool PRIMAL, int S>
-__device__ inline Row load_row(const PdArgs& a, long long base, int x, int r, bool in_x)
+__device__ inline Row load_row(const Planes& P, int x, int r, bool in_x)
 {
     Row w = zero_row();
-    if (in_x && r >= 0 && r < a.H) {
-        const size_t o = base + (size_t)r * a.pitch + x;
-        w.u = a.u_in[o];
-        w.p = ld2<S>(a.p_in, o);
-        w.t = ld4<S>(a.tpack, o);
-        w.f = a.flags[(size_t)r * a.pitch + x];
-        if (PRIMAL) w.rho = a.rho[o];
+    if (in_x && r >= 0 && r < P.H) {
+        const size_t o = (size_t)r * P.pitch + x;
+        w.u = P.u_in[o];
+        w.p = ld2<S>(P.p_in, o);
+        w.t = ld4<S>(P.tpack, o);
+        w.f = P.flags[o];
+        if (PRIMAL) w.rho = P.rho[o];
         if (TGV) {
-            w.v = a.v_in[o];
-            w.q = ld4<S>(a.q_in, o);
+            w.v = P.v_in[o];
+            w.q = ld4<S>(P.q_in, o);
         }
     }
     return w;
@@ -231,22 +279,23 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
     constexpr bool DUAL = MODE != PD_PRIMAL_LAST;
 
     const int logical = logical_block();
-    const int tiles_x = (a.W + kCols - 1) / kCols;
-    const int tiles_y = (a.H + kBY * kWaves - 1) / (kBY * kWaves);
+    const int tiles_x = (a.lc.g.W[a.lc.gl] + kCols - 1) / kCols;
+    const int tiles_y = (a.lc.g.H[a.lc.gl] + kBY * kWaves - 1) / (kBY * kWaves);
     const int tx = logical % tiles_x;
     const int ty = (logical / tiles_x) % tiles_y;
     const int pair = logical / (tiles_x * tiles_y);
-    if (pair >= a.n) return;
+    Planes P;
+    if (!planes_of<S>(a, pair, P)) return;
+    if (tx * kCols >= P.W) return;
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = threadIdx.x / kLanes;
     const int x = tx * kCols - 1 + lane;
-    const bool in_x = x >= 0 && x < a.W;
+    const bool in_x = x >= 0 && x < P.W;
     const bool owner = lane >= 1 && lane <= kCols && in_x;
     const int y0 = (ty * kWaves + wave) * kBY;
-    if (y0 >= a.H) return;
-    const int y1 = min(y0 + kBY, a.H);          // owned rows [y0, y1)
-    const long long base = (long long)pair * a.stride;
+    if (y0 >= P.H) return;
+    const int y1 = min(y0 + kBY, P.H);          // owned rows [y0, y1)
     const float a0 = a.alpha0, a1 = a.alpha1;
 
     // row r - 1 as the dual step needs it
@@ -257,22 +306,22 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
     float2 vb_prev = make_float2(0.f, 0.f);
     Above ab = {0.f, 0.f, 0.f, 0.f, 0.f};
     if (PRIMAL) {
-        const Row w = load_row<TGV, false, S>(a, base, x, y0 - 1, in_x);
+        const Row w = load_row<TGV, false, S>(P, x, y0 - 1, in_x);
         ab = above_of(w.p, w.q, w.t, w.f);
     }
 
     const int r_end = DUAL ? y1 : y1 - 1;       // last row visited (row y1 is the look-ahead)
     for (int r = y0; r <= r_end; ++r) {
-        const Row c = load_row<TGV, PRIMAL, S>(a, base, x, r, in_x);
+        const Row c = load_row<TGV, PRIMAL, S>(P, x, r, in_x);
         // primal step at row r: x^k from x^{k-1} and y^k
         float un = c.u;
         float2 vn = c.v;
         if (PRIMAL) {
             primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab, a0, a1, a.lambda, a.tau_scale, un, vn);
             if (owner && r < y1) {
-                const size_t o = base + (size_t)r * a.pitch + x;
-                a.u_out[o] = un;
-                if (TGV) a.v_out[o] = vn;
+                const size_t o = (size_t)r * P.pitch + x;
+                P.u_out[o] = un;
+                if (TGV) P.v_out[o] = vn;
             }
         }
         // over-relaxation (xbar stays in registers)
@@ -287,9 +336,9 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
                 float4 qn;
                 dual_step<TGV>(p_prev, q_prev, t_prev, f_prev, ub_prev, vb_prev, ub_r, vb_r, ub, vb, a0, a1,
                                a.sigma_scale, pn, qn);
-                const size_t o = base + (size_t)(r - 1) * a.pitch + x;
-                st2<S>(a.p_out, o, pn);
-                if (TGV) st4<S>(a.q_out, o, qn);
+                const size_t o = (size_t)(r - 1) * P.pitch + x;
+                st2<S>(P.p_out, o, pn);
+                if (TGV) st4<S>(P.q_out, o, qn);
             }
         }
         // slide the window
@@ -315,28 +364,29 @@ template <bool TGV, int S>
 __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
 {
     const int logical = logical_block();
-    const int tiles_x = (a.W + kCols2 - 1) / kCols2;
-    const int tiles_y = (a.H + kBY2 * kWaves - 1) / (kBY2 * kWaves);
+    const int tiles_x = (a.lc.g.W[a.lc.gl] + kCols2 - 1) / kCols2;
+    const int tiles_y = (a.lc.g.H[a.lc.gl] + kBY2 * kWaves - 1) / (kBY2 * kWaves);
     const int tx = logical % tiles_x;
     const int ty = (logical / tiles_x) % tiles_y;
     const int pair = logical / (tiles_x * tiles_y);
-    if (pair >= a.n) return;
+    Planes P;
+    if (!planes_of<S>(a, pair, P)) return;
+    if (tx * kCols2 >= P.W) return;
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = threadIdx.x / kLanes;
     const int x = tx * kCols2 - 2 + lane;
-    const bool in_x = x >= 0 && x < a.W;
+    const bool in_x = x >= 0 && x < P.W;
     const bool owner = lane >= 2 && lane <= kCols2 + 1 && in_x;
     const int y0 = (ty * kWaves + wave) * kBY2;
-    if (y0 >= a.H) return;
-    const int y1 = min(y0 + kBY2, a.H);
-    const long long base = (long long)pair * a.stride;
+    if (y0 >= P.H) return;
+    const int y1 = min(y0 + kBY2, P.H);
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
 
     // iteration 1: "above" of row r-1, and row r-1 as B needs it
     Above ab1;
     {
-        const Row w = load_row<TGV, false, S>(a, base, x, y0 - 2, in_x);
+        const Row w = load_row<TGV, false, S>(P, x, y0 - 2, in_x);
         ab1 = above_of(w.p, w.q, w.t, w.f);
     }
     float2 p_m1 = make_float2(0.f, 0.f);
@@ -363,7 +413,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
         float un1 = 0.f, ub1 = 0.f;
         float2 vn1 = make_float2(0.f, 0.f), vb1 = make_float2(0.f, 0.f);
         if (r <= y1 + 1) {
-            c = load_row<TGV, true, S>(a, base, x, r, in_x);
+            c = load_row<TGV, true, S>(P, x, r, in_x);
             primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, a.tau_scale, un1, vn1);
             ub1 = un1 + a.theta * (un1 - c.u);
             vb1 = make_float2(vn1.x + a.theta * (vn1.x - c.v.x), vn1.y + a.theta * (vn1.y - c.v.y));
@@ -388,9 +438,9 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
             ub2 = un2 + a.theta2 * (un2 - un1_m2);
             vb2 = make_float2(vn2.x + a.theta2 * (vn2.x - vn1_m2.x), vn2.y + a.theta2 * (vn2.y - vn1_m2.y));
             if (owner && r - 2 < y1) {
-                const size_t o = base + (size_t)(r - 2) * a.pitch + x;
-                a.u_out[o] = un2;
-                if (TGV) a.v_out[o] = vn2;
+                const size_t o = (size_t)(r - 2) * P.pitch + x;
+                P.u_out[o] = un2;
+                if (TGV) P.v_out[o] = vn2;
             }
         }
         // D: iteration-2 dual at row r-3 -> y^{k+2}(r-3)
@@ -402,9 +452,9 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
             dual_step<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1, a.sigma_scale2,
                            pn, qn);
             if (owner) {
-                const size_t o = base + (size_t)(r - 3) * a.pitch + x;
-                st2<S>(a.p_out, o, pn);
-                if (TGV) st4<S>(a.q_out, o, qn);
+                const size_t o = (size_t)(r - 3) * P.pitch + x;
+                st2<S>(P.p_out, o, pn);
+                if (TGV) st4<S>(P.q_out, o, qn);
             }
         }
         // slide the windows (deepest first)
@@ -438,18 +488,18 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
 template <int MODE, bool TGV, int S>
 void launch_mode(const PdArgs& a, hipStream_t s)
 {
-    const int tiles_x = (a.W + kCols - 1) / kCols;
-    const int tiles_y = (a.H + kBY * kWaves - 1) / (kBY * kWaves);
-    const int nb = tiles_x * tiles_y * a.n;
+    const int tiles_x = (a.lc.g.W[a.lc.gl] + kCols - 1) / kCols;
+    const int tiles_y = (a.lc.g.H[a.lc.gl] + kBY * kWaves - 1) / (kBY * kWaves);
+    const int nb = tiles_x * tiles_y * a.lc.n;
     hipLaunchKernelGGL((pd_kernel<MODE, TGV, S>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
 }
 
 template <bool TGV, int S>
 void launch_fused2(const PdArgs& a, hipStream_t s)
 {
-    const int tiles_x = (a.W + kCols2 - 1) / kCols2;
-    const int tiles_y = (a.H + kBY2 * kWaves - 1) / (kBY2 * kWaves);
-    const int nb = tiles_x * tiles_y * a.n;
+    const int tiles_x = (a.lc.g.W[a.lc.gl] + kCols2 - 1) / kCols2;
+    const int tiles_y = (a.lc.g.H[a.lc.gl] + kBY2 * kWaves - 1) / (kBY2 * kWaves);
+    const int nb = tiles_x * tiles_y * a.lc.n;
     hipLaunchKernelGGL((pd2_kernel<TGV, S>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
 }
 

@@ -197,50 +197,132 @@ template <int S> __device__ inline void st4(void* base, size_t i, float4 f)
     }
 }
 
+// ----------------------------------------------------------------- per-pair descriptors
+// Sizes of the pyramid levels and the element offset of each level inside a
+// level-stacked plane (levels stored one after the other, each with its own
+// pitch, a multiple of 64 elements).
+struct Geometry {
+    int L;
+    int W[kMaxLevels], H[kMaxLevels], pitch[kMaxLevels];
+    long long off[kMaxLevels];
+};
+
+// One pair's descriptor, read by every batched kernel from device memory.
+// Level-stacked arrays hold every level (level l at off[l]); single-level
+// arrays hold the level in use with that level's pitch.  Element sizes of p,
+// q and tpack follow the storage mode (FP32: 8, 16, 16 bytes; 16-bit: 4, 8, 8).
+struct Slot {
+    const float* I0;            // level-0 images (caller memory), pitch in_pitch
+    const float* I1;
+    int in_pitch;
+    int out_pitch;
+    float* u_out;               // outputs (caller memory, may be NULL), pitch out_pitch
+    float* w_out;               // interleaved (x, y)
+    float* depth_out;
+    float* z_out;
+    uint8_t* valid_out;
+    const float2* gamma[kMaxLevels];    // rig fields of every level (level pitch)
+    const uint8_t* flags[kMaxLevels];
+    const float2* calib;        // level-0 pre-rotation map
+    const RigGeom* geom;
+    float* J0;                  // level-stacked pyramids (J0 level 0: copy of I0)
+    float* J1;
+    float* u[2];                // level-stacked state, double-buffered
+    float2* v[2];
+    void* p[2];
+    void* q[2];
+    float2* w;                  // level-stacked, single
+    float* uw;                  // single-level
+    float2* gw;
+    void* tpack;
+    float* rho;
+    float beta, eta;
+};
+
+// Per-tick control of a slot in the serving loop (written between graph
+// replays).  ops: the stages of the tick the slot takes part in; level: the
+// level of the tick's warp step; warp: its index in the level; flip: parity
+// of the slot's double-buffered state relative to the launch's (bit 0 u/v,
+// bit 1 p/q).
+enum : uint8_t {
+    OP_START = 1u,      // pre-rotation, pyramids, zero state at the coarsest level
+    OP_NEWLEVEL = 2u,   // close level+1 (final accumulate) and transfer to level
+    OP_TENSOR = 4u,     // tensor of level
+    OP_WARP = 8u,       // linearise + K primal-dual iterations at level
+    OP_FINISH = 16u,    // final accumulate at level 0 and triangulation
+    OP_ALL = 0xffu,
+};
+struct Ctrl {
+    int8_t level;
+    uint8_t ops;
+    uint8_t flip;
+    uint8_t pad;
+    int32_t warp;
+};
+
+// Which pairs a launch covers and at which level.  tick = 0: pairs 0..n-1, all
+// at level lev, parity (iu, ip).  tick = 1 (serving): pair z takes part if
+// ctrl[z].ops & op, at level lev if lev >= 0 else ctrl[z].level + dl, with
+// parity (iu, ip) ^ ctrl[z].flip.  The grid covers the level-gl size.
+struct Launch {
+    const Slot* slots;
+    const Ctrl* ctrl;
+    int n;
+    int tick;
+    int lev, dl;
+    int gl;
+    unsigned op;
+    int iu, ip;
+    Geometry g;
+};
+
+struct Pick {
+    int l;
+    unsigned flip;
+    int warp;
+};
+
+__device__ inline bool pick(const Launch& lc, int z, Pick& pk)
+{
+    if (z >= lc.n) return false;
+    if (!lc.tick) {
+        pk.l = lc.lev;
+        pk.flip = 0u;
+        pk.warp = -1;
+        return true;
+    }
+    const Ctrl c = lc.ctrl[z];
+    if (!(c.ops & lc.op)) return false;
+    pk.l = lc.lev >= 0 ? lc.lev : c.level + lc.dl;
+    pk.flip = c.flip;
+    pk.warp = c.warp;
+    return pk.l >= 0 && pk.l < lc.g.L;
+}
+
 // ----------------------------------------------------------------- launchers
 // Set-up (double precision).
 void launch_calibration(const RigGeom& g, float2* calib, int pitch, hipStream_t s);
 void launch_level_fields(const RigGeom& g, int level, float2* gamma, uint8_t* flags, int pitch,
                          hipStream_t s);
 
-// Per-pair image steps (batched over pairs b < n with element strides).
-struct PairPtrs {
-    const float* in[kMaxBatch];
-    int in_pitch;       // elements
-};
-void launch_prerotate(const PairPtrs& I1, int n, int W, int H, const float2* calib, int cpitch,
-                      float* out, int opitch, long long ostride, hipStream_t s);
-void launch_downsample(int n, int Wc, int Hc, const float* const* fine, int fpitch, long long fstride,
-                       float* coarse, int cpitch, long long cstride, hipStream_t s);
-void launch_tensor(int n, int W, int H, const float* const* J0, int jpitch, long long jstride,
-                   const uint8_t* flags, int fpitch, const float* betas, const float* etas,
-                   void* tpack, int tpitch, long long tstride, int storage, hipStream_t s);
-void launch_linearise(int n, int W, int H, int pitch, long long stride, const float* const* J0,
-                      int j0pitch, long long j0stride, const float* J1, long long j1stride,
-                      const float2* gamma, const uint8_t* flags, float* u, float* u_w, float2* w,
-                      float2* gamma_w, void* tpack, float* rho, int clip, int clip_only, float du_max,
-                      int storage, hipStream_t s);
-void launch_upsample(int n, int Wc, int Hc, int cpitch, long long cstride, const uint8_t* flags_c,
-                     int fcpitch, const float* u_c, const float2* w_c, int fpitch, long long fstride,
-                     float* u_f, float2* w_f, float2* v_f, void* p_f, void* q_f, int storage, hipStream_t s);
-void launch_zero_state(int n, int W, int H, int pitch, long long stride, float* u, float2* w, float2* v,
-                       void* p, void* q, int storage, hipStream_t s);
-void launch_triangulate(int n, const RigGeom& g, int W, int H, int pitch, long long stride,
-                        const float* u, const float2* w, const uint8_t* flags, int fpitch,
-                        float* const* u_out, float* const* w_out, float* const* depth_out,
-                        float* const* z_out, uint8_t* const* valid_out, int opitch, hipStream_t s);
+// Descriptor writes (stream-ordered, graph-safe: kernels, not memsets).
+void launch_write_slot(const Slot& sl, Slot* dst, hipStream_t s);
+struct CtrlBlock { Ctrl c[kMaxBatch]; };
+void launch_write_ctrl(const CtrlBlock& cb, int n, Ctrl* dst, hipStream_t s);
+
+// Batched image steps; every launch takes a Launch (which pairs, which level).
+void launch_prerotate(const Launch& lc, hipStream_t s);                      // J1[0], J0[0] of level 0
+void launch_downsample(const Launch& lc, hipStream_t s);                     // J0, J1 level lev from lev - 1
+void launch_tensor(const Launch& lc, int storage, hipStream_t s);
+void launch_linearise(const Launch& lc, int clip, int clip_only, float du_max, int storage, hipStream_t s);
+void launch_upsample(const Launch& lc, int tgv, int storage, hipStream_t s);  // level + 1 -> level
+void launch_zero_state(const Launch& lc, int tgv, int storage, hipStream_t s);
+void launch_triangulate(const Launch& lc, hipStream_t s);                    // level 0
 
 // Primal-dual iteration (Eq. (11)).
 enum PdMode { PD_DUAL_FIRST = 0, PD_FUSED = 1, PD_PRIMAL_LAST = 2, PD_FUSED2 = 3 };
 struct PdArgs {
-    int W, H, pitch;            // level size, element pitch of every plane
-    long long stride;           // elements between pairs
-    int n;                      // pairs
-    const float* u_in; const float2* v_in; const void* p_in; const void* q_in;
-    float* u_out; float2* v_out; void* p_out; void* q_out;
-    const void* tpack;          // (t11, t12, t22, I_u)
-    const float* rho;           // rho_c
-    const uint8_t* flags;       // shared by all pairs (rig field)
+    Launch lc;                  // parity (lc.iu, lc.ip): the state read; the other copy is written
     float alpha0, alpha1, lambda;
     float tau_scale, sigma_scale, theta;     // iteration k (PD_FUSED2: the first of its two)
     float tau_scale2, sigma_scale2, theta2;  // PD_FUSED2: iteration k + 1
@@ -249,5 +331,19 @@ struct PdArgs {
     int storage;                // Storage of p, q and the tensor pack
 };
 void launch_pd(const PdArgs& a, hipStream_t s);
+
+// Linearised energy of Eq. (10) per pair of a launch (fixed-order FP64
+// reduction): partial needs energy_partials(lc) doubles, out lc.n doubles.
+struct EnergyConsts {
+    float lambda, alpha0, alpha1;
+    int tgv, storage;
+};
+size_t energy_partials(const Launch& lc);
+void launch_energy(const Launch& lc, const EnergyConsts& k, double* partial, double* out, hipStream_t s);
+// Sum, max and count of |a - b| over the mask bit of `mask` (all pixels if
+// NULL): partial needs 3 * diff_partials(W, H) doubles, out3 3 doubles.
+size_t diff_partials(int W, int H);
+void launch_diff_stats(int W, int H, int pitch, const float* a, const float* b, const uint8_t* mask,
+                       double* partial, double* out3, hipStream_t s);
 
 }  // namespace vfs

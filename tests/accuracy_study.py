@@ -1,0 +1,136 @@
+"""Accuracy studies against full FP64 oracle solves (a script, not collected
+by pytest; it needs a GPU and a few minutes of host CPU).
+
+  python -m tests.accuracy_study precision OUT.json
+      FP32 / FP16 / BF16 storage of one 1280x1024 190-degree pair (6 levels x
+      10 warps x 150 iterations) and of pair 0 of the 2048x2048 200-degree
+      batch (7 x 15 x 200): displacement and depth error against the oracle,
+      next to the conditioning floor (the FP32 solve of the input perturbed
+      by 1e-6 relative, against the unperturbed FP32 solve).
+
+  python -m tests.accuracy_study serving OUT.json
+      The serving workload's solver settings (10 warps x 50 iterations,
+      levels 4 / 5 / 5): one pair per (size, rig 0 / 1) served by the FP16
+      continuous-batching server and by the plain FP32 server, against the
+      oracle.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _errors(out, o, m):
+    import numpy as np
+    u = out["u"].cpu().numpy()
+    w = out["w"].cpu().numpy()
+    du = np.abs(u - o["u"])[m]
+    dw = np.linalg.norm(w - o["w"], axis=-1)[m]
+    vg = out["valid"].cpu().numpy().astype(bool)
+    both = vg & o["valid"].astype(bool)
+    rel = np.abs(out["depth"].cpu().numpy()[both] - o["depth"][both]) / o["depth"][both]
+    return {"u_mean": float(du.mean()), "u_p99": float(np.percentile(du, 99)), "u_max": float(du.max()),
+            "w_mean": float(dw.mean()), "depth_rel_median": float(np.median(rel)),
+            "depth_rel_p90": float(np.percentile(rel, 90)), "validity_flips": int(np.sum(vg != o["valid"]))}
+
+
+def precision():
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1909_07545_amd as vfs
+    from synth import configs, scene
+
+    table = {}
+    for cid in ("c3", "c5"):
+        cfg = configs.get(cid)
+        params = configs.solver_params(cfg)
+        rig = scene.make_rig(cfg)
+        log(f"precision: rendering {cid} pair 0")
+        I0, I1 = scene.render_pair(rig, cfg, 0, with_gt=False)[:2]
+        beta, eta = scene.pair_tensor_params(cfg, 0)
+        params = dict(params, beta=beta, eta=eta)
+        R = vfs.Rig(rig["cam0"], rig["cam1"], rig["R"], rig["t"], params["levels"])
+        t0, t1 = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
+        outs = {name: vfs.solve(R, t0, t1, dict(params, storage=st))
+                for name, st in (("f32", 0), ("f16", 1), ("bf16", 2))}
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        o = oracle.solve(rig["cam0"], rig["cam1"], rig["R"], rig["t"], params, I0.astype(np.float64),
+                         I1.astype(np.float64))
+        log(f"precision: {cid} oracle solve took {time.perf_counter() - t:.1f} s")
+        m = oracle.mask0(rig["cam0"]).astype(bool)
+        row = {name: _errors(out, o, m) for name, out in outs.items()}
+        rng = np.random.default_rng(0)
+        I0p = (I0.astype(np.float64) * (1 + 1e-6 * rng.standard_normal(I0.shape))).astype(np.float32)
+        outp = vfs.solve(R, torch.from_numpy(I0p).cuda(), t1, params)
+        d = np.abs(outp["u"].cpu().numpy() - outs["f32"]["u"].cpu().numpy())[m]
+        row["floor_f32_input_1e-6"] = {"u_mean": float(d.mean()), "u_p99": float(np.percentile(d, 99)),
+                                       "u_max": float(d.max())}
+        table[cid] = row
+        log(f"precision: {cid} {json.dumps(row)}")
+    return {"precision": table}
+
+
+def serving():
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1909_07545_amd as vfs
+    from synth import configs, serving as sv
+
+    sp = sv.spec()
+    rigs = sv.serving_rigs(sp)
+    pool = sv.render_pool(rigs, 1, sp)
+    base = configs.solver_params(dict(levels=1, warps=sp["warps"], iters=sp["iters"]))
+    rows = []
+    for s in range(len(sp["sizes"])):
+        for r in (0, 1):
+            rg = rigs[r][s]
+            h = vfs.Rig(rg["cam0"], rg["cam1"], rg["R"], rg["t"], rg["levels"])
+            I0, I1 = pool[(r, s)][0]
+            i0, i1 = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
+            got = {}
+            for name, st, mode in (("fp16_batched", 1, "batched"), ("fp32_plain", 0, "plain")):
+                params = dict(base, storage=st)
+                o = dict(u=torch.empty((h.height, h.width), device="cuda"),
+                         depth=torch.empty((h.height, h.width), device="cuda"))
+                with vfs.Server(params, mode=mode) as srv:
+                    srv.submit(h, i0, i1, o, params["beta"], params["eta"])
+                    srv.wait_all(600.0)
+                got[name] = o["u"].cpu().numpy()
+            t0 = time.perf_counter()
+            ref = oracle.solve(rg["cam0"], rg["cam1"], rg["R"], rg["t"], dict(base, levels=rg["levels"]),
+                               I0.astype(np.float64), I1.astype(np.float64))
+            m = oracle.mask0(rg["cam0"]).astype(bool)
+            row = {"size": f"{h.width}x{h.height}", "rig": r, "oracle_s": round(time.perf_counter() - t0, 1)}
+            for name, u in got.items():
+                d = np.abs(u - ref["u"])[m]
+                row[name] = {"u_mean": float(d.mean()), "u_p99": float(np.percentile(d, 99)),
+                             "u_max": float(d.max())}
+            rows.append(row)
+            log(f"serving accuracy: {json.dumps(row)}")
+    return {"serving_accuracy": rows}
+
+
+def main():
+    what, out = sys.argv[1], sys.argv[2]
+    res = precision() if what == "precision" else serving()
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

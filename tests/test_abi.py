@@ -85,3 +85,26 @@ def test_solve_and_steps_reject_bad_arguments(vfs):
                          None) == -1
     assert L.vfs_step_upsample(4, 4, 2, one, one, one, 8, one, one, None) == -1
     assert L.vfs_profile_enable(None, 1) == -1
+
+
+def test_server_rejects_bad_configuration(vfs):
+    L = vfs.lib()
+    cfg = vfs.ServerConfig()
+    assert L.vfs_server_config_default(ctypes.byref(cfg)) == 0
+    assert (cfg.mode, cfg.hbm_budget_bytes, cfg.max_slots, cfg.use_graphs) == (0, 1 << 30, 16, 1)
+    p = vfs._params(dict(vfs.default_params(), warps=10, iters=50))
+    h = ctypes.c_void_p()
+    for field, value in (("max_slots", 0), ("max_slots", 33), ("mode", 2), ("hbm_budget_bytes", 0)):
+        bad = vfs.ServerConfig(cfg.mode, cfg.hbm_budget_bytes, cfg.max_slots, cfg.use_graphs)
+        setattr(bad, field, value)
+        assert L.vfs_server_create(ctypes.byref(bad), ctypes.byref(p), ctypes.byref(h)) == -1, field
+    no_warps = vfs._params(dict(vfs.default_params(), warps=0))
+    assert L.vfs_server_create(ctypes.byref(cfg), ctypes.byref(no_warps), ctypes.byref(h)) == -1
+    assert "warps" in L.vfs_last_error().decode()
+    assert L.vfs_server_create(ctypes.byref(cfg), ctypes.byref(p), None) == -1
+    tk = ctypes.c_ulonglong()
+    assert L.vfs_server_submit(None, None, None, None, 0, None, None, None, None, None, 9.0, 0.85,
+                               ctypes.byref(tk)) == -1
+    done = ctypes.c_int()
+    assert L.vfs_server_poll(None, 1, ctypes.byref(done), None) == -1
+    assert L.vfs_server_wait_all(None, 1.0) == -1

@@ -1,0 +1,158 @@
+"""Serving loop (continuous batching) on the GPU: every request's outputs are
+bitwise those of solving it alone with vfs_solve; requests join while others
+are mid-solve; admission respects the HBM budget; graph replays equal eager
+ticks; the plain baseline equals the direct solve too.
+
+Workload: the serving rigs (Kannala-Brandt, 180 degrees, f = 0.34375 W) at
+two small sizes (160x120 with 3 levels, 320x240 with 4), rendered rooms,
+short schedules (3 warps; 5 and 6 iterations, whose primal-dual launch
+sequences leave the state in opposite buffers, so that both parities of the
+per-slot state are exercised).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+from synth import configs, serving
+
+pytestmark = pytest.mark.gpu
+
+SIZES = ((160, 120), (320, 240))
+LEVELS = (3, 4)
+
+
+@pytest.fixture(scope="module")
+def workload():
+    import torch
+    import paper_1909_07545_amd as vfs
+    sp = serving.spec()
+    sp.update(sizes=SIZES, levels=LEVELS, rigs=2)
+    rigs = serving.serving_rigs(sp)
+    pool = serving.render_pool(rigs, 1, sp)
+    handles = {}
+    for r, per in enumerate(rigs):
+        for s, rg in enumerate(per):
+            handles[(r, s)] = vfs.Rig(rg["cam0"], rg["cam1"], rg["R"], rg["t"], rg["levels"])
+    imgs = {k: [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for a, b in v] for k, v in pool.items()}
+    torch.cuda.synchronize()
+    return dict(rigs=handles, imgs=imgs)
+
+
+def _params(iters, storage):
+    return configs.solver_params(dict(levels=1, warps=3, iters=iters), storage=storage)
+
+
+def _requests(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        beta = float(rng.uniform(6.0, 12.0))
+        eta = float(rng.uniform(0.7, 1.0))
+        out.append(dict(rig=int(rng.integers(0, 2)), size=int(rng.integers(0, 2)), beta=beta, eta=eta))
+    return out
+
+
+def _outputs(H, W):
+    import torch
+    return dict(u=torch.full((H, W), float("nan"), device="cuda"),
+                w=torch.full((H, W, 2), float("nan"), device="cuda"),
+                depth=torch.full((H, W), float("nan"), device="cuda"),
+                z=torch.full((H, W), float("nan"), device="cuda"),
+                valid=torch.full((H, W), 7, dtype=torch.uint8, device="cuda"))
+
+
+def _alone(vfs, wl, req, params):
+    rig = wl["rigs"][(req["rig"], req["size"])]
+    I0, I1 = wl["imgs"][(req["rig"], req["size"])][0]
+    p = dict(params, levels=rig.levels)
+    return vfs.solve_batch(rig, [I0], [I1], p, betas=[req["beta"]], etas=[req["eta"]])[0]
+
+
+def _serve(vfs, wl, reqs, params, waves=2, gap_s=0.0005, **server_kw):
+    """Submit reqs in waves (the later ones while the first are running);
+    returns (outputs, tickets, submit times, server stats, times)."""
+    import torch
+    outs, tickets, t_sub = [], [], []
+    with vfs.Server(params, **server_kw) as srv:
+        per = (len(reqs) + waves - 1) // waves
+        for k, req in enumerate(reqs):
+            if k and k % per == 0:
+                time.sleep(gap_s)
+            rig = wl["rigs"][(req["rig"], req["size"])]
+            I0, I1 = wl["imgs"][(req["rig"], req["size"])][0]
+            o = _outputs(rig.height, rig.width)
+            outs.append(o)
+            t_sub.append(time.perf_counter())
+            tickets.append(srv.submit(rig, I0, I1, o, req["beta"], req["eta"]))
+        srv.wait_all(120.0)
+        times = [srv.times(t) for t in tickets]
+        lat = [srv.poll(t) for t in tickets]
+        stats = srv.stats()
+    torch.cuda.synchronize()
+    assert all(d for d, _ in lat)
+    return outs, tickets, t_sub, stats, times
+
+
+def _assert_equal(a, b, tag):
+    import torch
+    for k in ("u", "w", "depth", "z", "valid"):
+        assert torch.equal(a[k], b[k]), (tag, k, (a[k].float() - b[k].float()).abs().nan_to_num(0).max().item())
+
+
+@pytest.mark.parametrize("iters,storage", [(5, 1), (6, 1), (5, 0)])
+def test_mix_equals_alone(workload, iters, storage):
+    import paper_1909_07545_amd as vfs
+    params = _params(iters, storage)
+    reqs = _requests(12, 100 + iters + 10 * storage)
+    outs, tickets, t_sub, stats, times = _serve(vfs, workload, reqs, params, waves=3, max_slots=4)
+    for i, req in enumerate(reqs):
+        _assert_equal(outs[i], _alone(vfs, workload, req, params), i)
+    assert stats["buckets"] == 2
+    assert stats["peak_active"] >= 2
+    # continuous batching: later waves joined buckets whose requests were mid-solve
+    assert stats["joins"] >= 1
+    assert 0 < stats["full_ticks"] < stats["ticks"]
+
+
+def test_budget_admission(workload):
+    import paper_1909_07545_amd as vfs
+    params = _params(5, 1)
+    reqs = [dict(rig=k % 2, size=1, beta=9.0, eta=0.85) for k in range(6)]
+    with vfs.Server(params) as probe:
+        need = probe.request_bytes(workload["rigs"][(0, 1)])
+    budget = int(2.5 * need)
+    outs, tickets, t_sub, stats, times = _serve(vfs, workload, reqs, params, waves=1, hbm_budget_bytes=budget,
+                                                max_slots=8)
+    assert stats["peak_active"] == 2
+    assert stats["pool_peak_bytes"] <= budget
+    for i, req in enumerate(reqs):
+        _assert_equal(outs[i], _alone(vfs, workload, req, params), i)
+    # a single request larger than the budget is refused at submission
+    with vfs.Server(params, hbm_budget_bytes=need // 2) as srv:
+        rig = workload["rigs"][(0, 1)]
+        I0, I1 = workload["imgs"][(0, 1)][0]
+        with pytest.raises(vfs.VfsError, match="VFS_E_BUDGET"):
+            srv.submit(rig, I0, I1, _outputs(rig.height, rig.width), 9.0, 0.85)
+
+
+def test_graphs_equal_eager_ticks(workload):
+    import paper_1909_07545_amd as vfs
+    params = _params(5, 1)
+    reqs = _requests(8, 7)
+    a = _serve(vfs, workload, reqs, params, waves=2, max_slots=3, use_graphs=True)[0]
+    b = _serve(vfs, workload, reqs, params, waves=2, max_slots=3, use_graphs=False)[0]
+    for i in range(len(reqs)):
+        _assert_equal(a[i], b[i], i)
+
+
+def test_plain_mode_equals_alone(workload):
+    import paper_1909_07545_amd as vfs
+    params = _params(6, 0)
+    reqs = _requests(5, 11)
+    outs, tickets, t_sub, stats, times = _serve(vfs, workload, reqs, params, waves=1, mode="plain")
+    assert stats["peak_active"] == 1
+    for i, req in enumerate(reqs):
+        _assert_equal(outs[i], _alone(vfs, workload, req, params), i)
