@@ -26,16 +26,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic (compulsory) HBM bytes per pixel of one launch of the level-0
-# primal-dual kernel, which carries two iterations of Eq. (11) per pass over
-# memory: reads u 4, v 8, p 8, q 16, tensor pack 16, rho_c 4, flags 1 (57 B);
-# writes u 4, v 8, p 8, q 16 (36 B).  Per pixel-iteration that is 46.5 B; the
-# textbook state (with ubar, vbar in memory) would move 117 B per
+# primal-dual pass, which carries several iterations of Eq. (11) (the
+# library reports how many) in one pass over memory: reads u 4, v 8, p 8,
+# q 16, tensor pack 16, rho_c 4, flags 1 (57 B); writes u 4, v 8, p 8, q 16
+# (36 B).  The textbook state (with ubar, vbar in memory) would move 117 B per
 # pixel-iteration.
 BYTES_PER_PIX_LAUNCH = 93
 # The same kernel with p, q and the tensor pack stored as 16-bit values:
 # reads u 4, v 8, p 4, q 8, tensor pack 8, rho_c 4, flags 1; writes u 4, v 8, p 4, q 8.
 BYTES_PER_PIX_LAUNCH_16 = 61
-ITERS_PER_LAUNCH = 2
 TEXTBOOK_BYTES_PER_PIX_ITER = 117
 HBM_PEAK_GBS = 8000.0
 
@@ -122,7 +121,7 @@ def main():
         outs = vfs.solve_batch(R, I0s, I1s, params, betas=betas, etas=etas, out=outs)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    pd_ms, pd_launches = vfs.profile_read(R, reset=True)
+    pd_ms, pd_launches, iters_per_launch = vfs.profile_read(R, reset=True)
     vfs.profile_enable(R, False)
     log(f"bench: {args.steps} timed steps in {dt:.3f} s")
 
@@ -134,14 +133,16 @@ def main():
     avg_launch_s = (pd_ms / pd_launches) / 1e3 if pd_launches else float("nan")
     bytes_per_launch = BYTES_PER_PIX_LAUNCH * W * H * n
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    effective = TEXTBOOK_BYTES_PER_PIX_ITER * ITERS_PER_LAUNCH * W * H * n / avg_launch_s / 1e9
+    effective = TEXTBOOK_BYTES_PER_PIX_ITER * iters_per_launch * W * H * n / avg_launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.config),
-                "kernel": "pd2_kernel<TGV> at level 0 (two primal-dual iterations per launch)",
+                "kernel": f"level-0 primal-dual pass ({iters_per_launch} iterations of Eq. (11) per launch, "
+                          f"{'pd2_kernel' if iters_per_launch == 2 else 'pdn_kernel'}<TGV>)",
+                "iters_per_launch": iters_per_launch,
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": pd_launches,
                 "bytes_per_launch": bytes_per_launch,
                 "effective_textbook_GBs": round(effective, 1),
-                "level0_Mpix_iter_s": round(ITERS_PER_LAUNCH * W * H * n / avg_launch_s / 1e6, 1)}
+                "level0_Mpix_iter_s": round(iters_per_launch * W * H * n / avg_launch_s / 1e6, 1)}
 
     fp16 = None
     if not args.no_fp16:
@@ -155,7 +156,7 @@ def main():
             outs16 = vfs.solve_batch(R, I0s, I1s, p16, betas=betas, etas=etas, out=outs16)
         torch.cuda.synchronize()
         dt16 = time.perf_counter() - t0
-        ms16, n16 = vfs.profile_read(R, reset=True)
+        ms16, n16, _ = vfs.profile_read(R, reset=True)
         vfs.profile_enable(R, False)
         a16 = (ms16 / n16) / 1e3 if n16 else float("nan")
         du = torch.stack([(o16["u"] - o["u"]).abs().mean() for o16, o in zip(outs16, outs)]).mean().item()

@@ -221,13 +221,15 @@ vfs_status vfs_diff_stats(int width, int height, size_t pitch, const float* a, c
                           void* hip_stream);
 
 /* ---- Measurement: when enabled, vfs_solve_batch records HIP events on its
- * stream around the level-0 primal-dual launches that each carry two
- * iterations of Eq. (11) (the dominant kernel) and accumulates their elapsed
- * time.  vfs_profile_read synchronises the stream of the last solve and
- * returns the accumulated milliseconds and the number of those launches
- * (counts since the last reset). */
+ * stream around the level-0 primal-dual launches that each carry several
+ * iterations of Eq. (11) in one pass over memory (the dominant kernel) and
+ * accumulates their elapsed time.  vfs_profile_read synchronises the stream
+ * of the last solve and returns the accumulated milliseconds, the number of
+ * those launches (counts since the last reset) and the iterations each
+ * launch carries (host outputs, each may be NULL). */
 vfs_status vfs_profile_enable(vfs_rig* rig, int enable);
-vfs_status vfs_profile_read(vfs_rig* rig, double* pd0_ms, long long* pd0_launches, int reset);
+vfs_status vfs_profile_read(vfs_rig* rig, double* pd0_ms, long long* pd0_launches, int* iters_per_launch,
+                            int reset);
 
 /* ---- Serving: a request loop that batches stereo pairs of different
  * sizes and rigs as they arrive (continuous batching).

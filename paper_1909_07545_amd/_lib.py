@@ -80,7 +80,7 @@ def lib():
                                         ctypes.c_size_t, _vp, _vp, _vp]
         L.vfs_step_triangulate.argtypes = [_vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
         L.vfs_profile_enable.argtypes = [_vp, ctypes.c_int]
-        L.vfs_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+        L.vfs_profile_read.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int]
         L.vfs_params_default.argtypes = [_vp]
         L.vfs_step_energy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t] + [_vp] * 7 + [_vp]
         L.vfs_step_pd_energy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t] + [_vp] * 11 + \
@@ -288,10 +288,13 @@ def profile_enable(rig: Rig, on: bool = True):
 
 
 def profile_read(rig: Rig, reset: bool = True):
+    """(milliseconds, launches, iterations per launch) of the level-0
+    multi-iteration primal-dual launches since the last reset."""
     ms = ctypes.c_double()
     n = ctypes.c_longlong()
-    _check(lib().vfs_profile_read(rig.handle, ctypes.byref(ms), ctypes.byref(n), int(reset)))
-    return ms.value, n.value
+    it = ctypes.c_int()
+    _check(lib().vfs_profile_read(rig.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(it), int(reset)))
+    return ms.value, n.value, it.value
 
 
 class Server:

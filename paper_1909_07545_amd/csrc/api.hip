@@ -2,6 +2,7 @@
 // level-0 primal-dual timing.  Host code only enqueues work; the solve never
 // waits on the device.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -227,6 +228,35 @@ vfs_status check_params(const vfs_params* p)
     return VFS_OK;
 }
 
+// Iterations per pass of the dominant primal-dual launches of a solve (a
+// batch or a serving bucket: n pairs whose level 0 is g's).  Measured on
+// MI355X: three iterations per pass (FP32: 3 wavefronts per SIMD; 16-bit
+// modes: 4) are faster where the passes are bandwidth-bound, from about
+// 16 M level-0 pixels per launch; below that the launches are latency-bound
+// and the shorter two-iteration march is faster.  VFS_PD_PASS=2|3|4
+// overrides the choice for measurements.
+int pd_pass_iters(const Geometry& g, int n)
+{
+    static const int forced = [] {
+        const char* e = getenv("VFS_PD_PASS");
+        const int v = e ? atoi(e) : 0;
+        return v >= 2 && v <= 4 ? v : 0;
+    }();
+    if (forced) return forced;
+    const long long px = (long long)g.W[0] * g.H[0] * n;
+    return px >= (16ll << 20) ? 3 : 2;
+}
+
+void pd_parity(int K, int NP, int& pu, int& pp)
+{
+    pu = pp = 0;
+    if (K <= 0) return;
+    const int rem = (K - 1) % NP, passes = (K - 1) / NP;
+    const int both = rem % 2 + rem / 2 + passes;  // launches that flip both copies
+    pp = (1 + both) & 1;                           // plus the first (dual only)
+    pu = (both + 1) & 1;                           // plus the last (primal only)
+}
+
 int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     iu = base.lc.iu;
@@ -244,9 +274,12 @@ int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s,
     a.theta = 1.f;
     go();
     ip ^= 1;
-    // iterations 1 .. K-1: an odd one alone, then pairs in one pass each
+    // iterations 1 .. K-1: the remainder first (one alone, then a pair),
+    // then passes of NP iterations each
+    const int NP = pd_pass_iters(base.lc.g, base.lc.n);
     int k = 1;
-    if ((K - 1) % 2) {
+    int rem = (K - 1) % NP;
+    if (rem % 2) {
         a.mode = PD_FUSED;
         a.tau_scale = sc.s[k - 1];
         a.theta = sc.theta[k - 1];
@@ -255,10 +288,9 @@ int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s,
         iu ^= 1;
         ip ^= 1;
         ++k;
+        --rem;
     }
-    if (ev0) (void)hipEventRecord(ev0, s);
-    int pairs = 0;
-    for (; k + 1 <= K - 1; k += 2, ++pairs) {
+    for (; rem >= 2; rem -= 2, k += 2) {
         a.mode = PD_FUSED2;
         a.tau_scale = sc.s[k - 1];
         a.theta = sc.theta[k - 1];
@@ -270,6 +302,29 @@ int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s,
         iu ^= 1;
         ip ^= 1;
     }
+    if (ev0) (void)hipEventRecord(ev0, s);
+    int passes = 0;
+    for (; k + NP - 1 <= K - 1; k += NP, ++passes) {
+        if (NP == 2) {
+            a.mode = PD_FUSED2;
+            a.tau_scale = sc.s[k - 1];
+            a.theta = sc.theta[k - 1];
+            a.sigma_scale = 1.f / sc.s[k];
+            a.tau_scale2 = sc.s[k];
+            a.theta2 = sc.theta[k];
+            a.sigma_scale2 = 1.f / sc.s[k + 1];
+        } else {
+            a.mode = NP == 3 ? PD_FUSED3 : PD_FUSED4;
+            for (int i = 0; i < NP; ++i) {
+                a.tau_n[i] = sc.s[k + i - 1];
+                a.theta_n[i] = sc.theta[k + i - 1];
+                a.sigma_n[i] = 1.f / sc.s[k + i];
+            }
+        }
+        go();
+        iu ^= 1;
+        ip ^= 1;
+    }
     if (ev1) (void)hipEventRecord(ev1, s);
     a.mode = PD_PRIMAL_LAST;
     a.tau_scale = sc.s[K - 1];
@@ -277,7 +332,7 @@ int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s,
     a.theta = 1.f;
     go();
     iu ^= 1;
-    return pairs;
+    return passes;
 }
 
 PdArgs pd_args(const Launch& lc, const vfs_params& params)
@@ -498,6 +553,7 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
         sl.eta = float(etas ? etas[b] : params->eta);
         launch_write_slot(sl, r->ws.slots + b, s);
     }
+    r->pass_iters = pd_pass_iters(r->g, n);
     return solve_slots(r->ws.slots, n, r->g, *params, s, r);
 }
 
@@ -903,8 +959,9 @@ vfs_status vfs_profile_enable(vfs_rig* r, int enable)
     return VFS_OK;
 }
 
-vfs_status vfs_profile_read(vfs_rig* r, double* ms, long long* launches, int reset)
+vfs_status vfs_profile_read(vfs_rig* r, double* ms, long long* launches, int* iters_per_launch, int reset)
 {
+    if (iters_per_launch) *iters_per_launch = r->pass_iters;
     g_err[0] = 0;
     if (!r) return fail(VFS_E_INVALID, "rig is NULL");
     if (!r->events.empty()) {

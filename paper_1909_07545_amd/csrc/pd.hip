@@ -50,9 +50,14 @@ namespace {
 constexpr int kLanes = 64;
 constexpr int kWaves = 4;            // wavefronts per workgroup
 constexpr int kCols = kLanes - 2;    // owned columns per wavefront, one-iteration modes
-constexpr int kBY = VFS_PD_BY;       // owned rows per wavefront, one-iteration modes
+constexpr int kBY = VFS_PD_BY;       // owned rows per wavefront, one-iteration modes (large grids)
 constexpr int kCols2 = kLanes - 4;   // owned columns per wavefront, PD_FUSED2
-constexpr int kBY2 = VFS_PD2_BY;     // owned rows per wavefront, PD_FUSED2
+constexpr int kBY2 = VFS_PD2_BY;     // owned rows per wavefront, PD_FUSED2 (large grids)
+// Small grids (few workgroups: coarse levels, small images) cannot hide the
+// memory latency of each row step of the march behind other wavefronts; they
+// march kBYs rows instead, for 4x the wavefronts and a shorter march.
+constexpr int kBYs = 4;
+constexpr long long kSmallGrid = 2048;   // workgroups at the large-grid height below which kBYs is used
 constexpr int kXcds = 8;
 
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -272,7 +277,7 @@ __device__ inline int logical_block()
 }
 
 // One iteration (PD_FUSED) or its first / last half (PD_DUAL_FIRST, PD_PRIMAL_LAST).
-template <int MODE, bool TGV, int S>
+template <int MODE, bool TGV, int S, int BY>
 __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
 {
     constexpr bool PRIMAL = MODE != PD_DUAL_FIRST;
@@ -280,7 +285,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
 
     const int logical = logical_block();
     const int tiles_x = (a.lc.g.W[a.lc.gl] + kCols - 1) / kCols;
-    const int tiles_y = (a.lc.g.H[a.lc.gl] + kBY * kWaves - 1) / (kBY * kWaves);
+    const int tiles_y = (a.lc.g.H[a.lc.gl] + BY * kWaves - 1) / (BY * kWaves);
     const int tx = logical % tiles_x;
     const int ty = (logical / tiles_x) % tiles_y;
     const int pair = logical / (tiles_x * tiles_y);
@@ -293,9 +298,9 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
     const int x = tx * kCols - 1 + lane;
     const bool in_x = x >= 0 && x < P.W;
     const bool owner = lane >= 1 && lane <= kCols && in_x;
-    const int y0 = (ty * kWaves + wave) * kBY;
+    const int y0 = (ty * kWaves + wave) * BY;
     if (y0 >= P.H) return;
-    const int y1 = min(y0 + kBY, P.H);          // owned rows [y0, y1)
+    const int y1 = min(y0 + BY, P.H);           // owned rows [y0, y1)
     const float a0 = a.alpha0, a1 = a.alpha1;
 
     // row r - 1 as the dual step needs it
@@ -311,8 +316,12 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
     }
 
     const int r_end = DUAL ? y1 : y1 - 1;       // last row visited (row y1 is the look-ahead)
+    // rows are loaded one step ahead of their use, so that a row's memory
+    // latency overlaps the previous row's arithmetic
+    Row nxt = load_row<TGV, PRIMAL, S>(P, x, y0, in_x);
     for (int r = y0; r <= r_end; ++r) {
-        const Row c = load_row<TGV, PRIMAL, S>(P, x, r, in_x);
+        const Row c = nxt;
+        if (r + 1 <= r_end) nxt = load_row<TGV, PRIMAL, S>(P, x, r + 1, in_x);
         // primal step at row r: x^k from x^{k-1} and y^k
         float un = c.u;
         float2 vn = c.v;
@@ -360,12 +369,12 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
 // read for A's first "above").  Column validity shrinks by one lane per
 // stage away from the wavefront's edges: A is exact on lanes 1..63, B on
 // 1..62, C on 2..62, D on 2..61 -- the owned lanes.
-template <bool TGV, int S>
+template <bool TGV, int S, int BY>
 __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
 {
     const int logical = logical_block();
     const int tiles_x = (a.lc.g.W[a.lc.gl] + kCols2 - 1) / kCols2;
-    const int tiles_y = (a.lc.g.H[a.lc.gl] + kBY2 * kWaves - 1) / (kBY2 * kWaves);
+    const int tiles_y = (a.lc.g.H[a.lc.gl] + BY * kWaves - 1) / (BY * kWaves);
     const int tx = logical % tiles_x;
     const int ty = (logical / tiles_x) % tiles_y;
     const int pair = logical / (tiles_x * tiles_y);
@@ -378,9 +387,9 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
     const int x = tx * kCols2 - 2 + lane;
     const bool in_x = x >= 0 && x < P.W;
     const bool owner = lane >= 2 && lane <= kCols2 + 1 && in_x;
-    const int y0 = (ty * kWaves + wave) * kBY2;
+    const int y0 = (ty * kWaves + wave) * BY;
     if (y0 >= P.H) return;
-    const int y1 = min(y0 + kBY2, P.H);
+    const int y1 = min(y0 + BY, P.H);
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
 
     // iteration 1: "above" of row r-1, and row r-1 as B needs it
@@ -407,13 +416,16 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
     float ub2_m3 = 0.f;
     float2 vb2_m3 = make_float2(0.f, 0.f);
 
+    // rows are loaded one step ahead of their use (see pd_kernel)
+    Row nxt = load_row<TGV, true, S>(P, x, y0 - 1, in_x);
     for (int r = y0 - 1; r <= y1 + 2; ++r) {
         // A: iteration-1 primal at row r
         Row c = zero_row();
         float un1 = 0.f, ub1 = 0.f;
         float2 vn1 = make_float2(0.f, 0.f), vb1 = make_float2(0.f, 0.f);
         if (r <= y1 + 1) {
-            c = load_row<TGV, true, S>(P, x, r, in_x);
+            c = nxt;
+            if (r + 1 <= y1 + 1) nxt = load_row<TGV, true, S>(P, x, r + 1, in_x);
             primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, a.tau_scale, un1, vn1);
             ub1 = un1 + a.theta * (un1 - c.u);
             vb1 = make_float2(vn1.x + a.theta * (vn1.x - c.v.x), vn1.y + a.theta * (vn1.y - c.v.y));
@@ -485,22 +497,234 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
     }
 }
 
+// N iterations per pass (PD_FUSEDN): (x^{k-1}, y^k) -> (x^{k+N-1}, y^{k+N}),
+// the generalisation of pd2_kernel.  At march step r, iteration i (0-based)
+// takes its primal step at row r - 2i and its dual step at row r - 2i - 1.
+// Iteration i's primal step reads x^{k+i-1} from iteration i-1's primal step
+// two steps earlier, y^{k+i} from iteration i-1's dual step one step earlier
+// (and two steps earlier for the row above); its dual step reads its own
+// xbar of the previous and the current step.  Iteration i covers rows
+// [y0 - (N-1-i), y1 + (N-1-i)] (primal) and one row fewer below (dual), so
+// the last iteration produces exactly the owned rows [y0, y1).  Column
+// validity shrinks by one lane per iteration on each side: the wavefront
+// owns lanes N .. 63-N.  The row constants (tensor, rho_c, flags) of the
+// last 2N rows stay in registers.
+// The tensor pack as kept in a register delay line: FP32 as is, the 16-bit
+// modes packed (as stored) and decoded at each use.
+template <int S> struct TensorRaw {
+    using type = uint2;
+    __device__ static uint2 pack(float4 t)
+    {
+        return make_uint2(uint32_t(enc16<S>(t.x)) | (uint32_t(enc16<S>(t.y)) << 16),
+                          uint32_t(enc16<S>(t.z)) | (uint32_t(enc16<S>(t.w)) << 16));
+    }
+    __device__ static float4 unpack(uint2 v)
+    {
+        return make_float4(dec16<S>(uint16_t(v.x & 0xffffu)), dec16<S>(uint16_t(v.x >> 16)),
+                           dec16<S>(uint16_t(v.y & 0xffffu)), dec16<S>(uint16_t(v.y >> 16)));
+    }
+    __device__ static uint2 identity() { return pack(make_float4(1.f, 0.f, 1.f, 0.f)); }
+};
+template <> struct TensorRaw<ST_F32> {
+    using type = float4;
+    __device__ static float4 pack(float4 t) { return t; }
+    __device__ static float4 unpack(float4 t) { return t; }
+    __device__ static float4 identity() { return make_float4(1.f, 0.f, 1.f, 0.f); }
+};
+
+template <bool TGV, int S, int BY, int N>
+__global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) void pdn_kernel(PdArgs a)
+{
+    constexpr int kColsN = kLanes - 2 * N;
+    constexpr int D = 2 * N;    // depth of the constants' delay line
+    const int logical = logical_block();
+    const int tiles_x = (a.lc.g.W[a.lc.gl] + kColsN - 1) / kColsN;
+    const int tiles_y = (a.lc.g.H[a.lc.gl] + BY * kWaves - 1) / (BY * kWaves);
+    const int tx = logical % tiles_x;
+    const int ty = (logical / tiles_x) % tiles_y;
+    const int pair = logical / (tiles_x * tiles_y);
+    Planes P;
+    if (!planes_of<S>(a, pair, P)) return;
+    if (tx * kColsN >= P.W) return;
+
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int wave = threadIdx.x / kLanes;
+    const int x = tx * kColsN - N + lane;
+    const bool in_x = x >= 0 && x < P.W;
+    const bool owner = lane >= N && lane < N + kColsN && in_x;
+    const int y0 = (ty * kWaves + wave) * BY;
+    if (y0 >= P.H) return;
+    const int y1 = min(y0 + BY, P.H);
+    const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
+
+    // constants of rows r - d (d = 0 .. D-1) after the shift of step r: the
+    // tensor pack as stored (16-bit modes keep it packed until use), rho_c,
+    // and the flag bytes packed 8 bits per row into one 64-bit shift register
+    using TRaw = typename TensorRaw<S>::type;
+    TRaw tD[D];
+    float rhoD[D];
+    uint64_t fD = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        tD[d] = TensorRaw<S>::identity();
+        rhoD[d] = 0.f;
+    }
+    auto flag = [&](int d) { return unsigned(fD >> (8 * d)) & 0xffu; };
+    // per iteration i: its primal outputs x of the last two steps, its xbar
+    // of the last step, its dual outputs y of the last two steps
+    float xu[N][2], xbu[N];
+    float2 xv[N][2], xbv[N], yp[N][2];
+    float4 yq[N][2];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        xbu[i] = 0.f;
+        xbv[i] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            xu[i][k] = 0.f;
+            xv[i][k] = make_float2(0.f, 0.f);
+            yp[i][k] = make_float2(0.f, 0.f);
+            yq[i][k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+    // y^k of the row above the current one (from memory), for iteration 0
+    float2 p_m1;
+    float4 q_m1;
+    {
+        const Row w = load_row<TGV, false, S>(P, x, y0 - N, in_x);
+        p_m1 = w.p;
+        q_m1 = w.q;
+        tD[0] = TensorRaw<S>::pack(w.t);
+        fD = w.f;
+    }
+    const int r_lo = y0 - (N - 1), r_hi = y1 + 2 * N - 2, r_load = y1 + N - 1;
+    Row nxt = load_row<TGV, true, S>(P, x, r_lo, in_x);
+    for (int r = r_lo; r <= r_hi; ++r) {
+        Row c = zero_row();
+        if (r <= r_load) {
+            c = nxt;
+            if (r + 1 <= r_load) nxt = load_row<TGV, true, S>(P, x, r + 1, in_x);
+        }
+#pragma unroll
+        for (int d = D - 1; d > 0; --d) {
+            tD[d] = tD[d - 1];
+            rhoD[d] = rhoD[d - 1];
+        }
+        tD[0] = TensorRaw<S>::pack(c.t);
+        rhoD[0] = c.rho;
+        fD = (fD << 8) | c.f;
+
+        float xnu[N], xbnu[N];
+        float2 xnv[N], xbnv[N], ynp[N];
+        float4 ynq[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int lo = y0 - (N - 1 - i), hi = y1 + (N - 1 - i);
+            // primal step of iteration i at row r - 2i
+            const int pr = r - 2 * i;
+            const float u_in = i == 0 ? c.u : xu[i - 1][1];
+            const float2 v_in = i == 0 ? c.v : xv[i - 1][1];
+            const float2 p_in = i == 0 ? c.p : yp[i - 1][0];
+            const float4 q_in = i == 0 ? c.q : yq[i - 1][0];
+            const float4 t_ab = TensorRaw<S>::unpack(tD[2 * i + 1]);
+            const Above ab = i == 0 ? above_of(p_m1, q_m1, t_ab, flag(1))
+                                    : above_of(yp[i - 1][1], yq[i - 1][1], t_ab, flag(2 * i + 1));
+            xnu[i] = 0.f;
+            xnv[i] = make_float2(0.f, 0.f);
+            xbnu[i] = 0.f;
+            xbnv[i] = make_float2(0.f, 0.f);
+            if (pr >= lo && pr <= hi) {
+                float un;
+                float2 vn;
+                primal_step<TGV>(u_in, v_in, p_in, q_in, i == 0 ? c.t : TensorRaw<S>::unpack(tD[2 * i]),
+                                 rhoD[2 * i], flag(2 * i), ab, a0, a1, lam, a.tau_n[i], un, vn);
+                const float th = a.theta_n[i];
+                xnu[i] = un;
+                xnv[i] = vn;
+                xbnu[i] = un + th * (un - u_in);
+                xbnv[i] = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
+                if (i == N - 1 && owner && pr >= y0 && pr < y1) {
+                    const size_t o = (size_t)pr * P.pitch + x;
+                    P.u_out[o] = un;
+                    if (TGV) P.v_out[o] = vn;
+                }
+            }
+            // dual step of iteration i at row r - 2i - 1
+            const int dr = pr - 1;
+            ynp[i] = make_float2(0.f, 0.f);
+            ynq[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (dr >= lo && dr <= hi - 1) {
+                const float2 py = i == 0 ? p_m1 : yp[i - 1][1];
+                const float4 qy = i == 0 ? q_m1 : yq[i - 1][1];
+                const float ub_r = from_right(xbu[i]);
+                const float2 vb_r = make_float2(from_right(xbv[i].x), from_right(xbv[i].y));
+                dual_step<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, xbnu[i], xbnv[i], a0, a1,
+                               a.sigma_n[i], ynp[i], ynq[i]);
+                if (i == N - 1 && owner && dr >= y0 && dr < y1) {
+                    const size_t o = (size_t)dr * P.pitch + x;
+                    st2<S>(P.p_out, o, ynp[i]);
+                    if (TGV) st4<S>(P.q_out, o, ynq[i]);
+                }
+            }
+        }
+        // slide the windows
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            xu[i][1] = xu[i][0];
+            xu[i][0] = xnu[i];
+            xv[i][1] = xv[i][0];
+            xv[i][0] = xnv[i];
+            xbu[i] = xbnu[i];
+            xbv[i] = xbnv[i];
+            yp[i][1] = yp[i][0];
+            yp[i][0] = ynp[i];
+            yq[i][1] = yq[i][0];
+            yq[i][0] = ynq[i];
+        }
+        p_m1 = c.p;
+        q_m1 = c.q;
+    }
+}
+
+// Workgroups of a launch whose wavefronts own `cols` columns and `by` rows.
+inline long long grid_blocks(const PdArgs& a, int cols, int by)
+{
+    const long long tiles_x = (a.lc.g.W[a.lc.gl] + cols - 1) / cols;
+    const long long tiles_y = (a.lc.g.H[a.lc.gl] + by * kWaves - 1) / (by * kWaves);
+    return tiles_x * tiles_y * a.lc.n;
+}
+
 template <int MODE, bool TGV, int S>
 void launch_mode(const PdArgs& a, hipStream_t s)
 {
-    const int tiles_x = (a.lc.g.W[a.lc.gl] + kCols - 1) / kCols;
-    const int tiles_y = (a.lc.g.H[a.lc.gl] + kBY * kWaves - 1) / (kBY * kWaves);
-    const int nb = tiles_x * tiles_y * a.lc.n;
-    hipLaunchKernelGGL((pd_kernel<MODE, TGV, S>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
+    const long long nb = grid_blocks(a, kCols, kBY);
+    if (nb >= kSmallGrid)
+        hipLaunchKernelGGL((pd_kernel<MODE, TGV, S, kBY>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
+    else
+        hipLaunchKernelGGL((pd_kernel<MODE, TGV, S, kBYs>), dim3(grid_blocks(a, kCols, kBYs)),
+                           dim3(kLanes * kWaves), 0, s, a);
 }
 
 template <bool TGV, int S>
 void launch_fused2(const PdArgs& a, hipStream_t s)
 {
-    const int tiles_x = (a.lc.g.W[a.lc.gl] + kCols2 - 1) / kCols2;
-    const int tiles_y = (a.lc.g.H[a.lc.gl] + kBY2 * kWaves - 1) / (kBY2 * kWaves);
-    const int nb = tiles_x * tiles_y * a.lc.n;
-    hipLaunchKernelGGL((pd2_kernel<TGV, S>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
+    const long long nb = grid_blocks(a, kCols2, kBY2);
+    if (nb >= kSmallGrid)
+        hipLaunchKernelGGL((pd2_kernel<TGV, S, kBY2>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
+    else
+        hipLaunchKernelGGL((pd2_kernel<TGV, S, kBYs>), dim3(grid_blocks(a, kCols2, kBYs)),
+                           dim3(kLanes * kWaves), 0, s, a);
+}
+
+template <bool TGV, int S, int N>
+void launch_fusedn(const PdArgs& a, hipStream_t s)
+{
+    const long long nb = grid_blocks(a, kLanes - 2 * N, kBY2);
+    if (nb >= kSmallGrid)
+        hipLaunchKernelGGL((pdn_kernel<TGV, S, kBY2, N>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
+    else
+        hipLaunchKernelGGL((pdn_kernel<TGV, S, kBYs, N>), dim3(grid_blocks(a, kLanes - 2 * N, kBYs)),
+                           dim3(kLanes * kWaves), 0, s, a);
 }
 
 template <bool TGV, int S>
@@ -509,6 +733,8 @@ void launch_typed(const PdArgs& a, hipStream_t s)
     if (a.mode == PD_DUAL_FIRST) launch_mode<PD_DUAL_FIRST, TGV, S>(a, s);
     else if (a.mode == PD_FUSED) launch_mode<PD_FUSED, TGV, S>(a, s);
     else if (a.mode == PD_FUSED2) launch_fused2<TGV, S>(a, s);
+    else if (a.mode == PD_FUSED3) launch_fusedn<TGV, S, 3>(a, s);
+    else if (a.mode == PD_FUSED4) launch_fusedn<TGV, S, 4>(a, s);
     else launch_mode<PD_PRIMAL_LAST, TGV, S>(a, s);
 }
 

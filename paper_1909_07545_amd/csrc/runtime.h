@@ -65,6 +65,7 @@ struct vfs_rig {
     bool profile = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     long long launches = 0;
+    int pass_iters = 2;                 // iterations per profiled launch (last solve)
     double ms = 0.0;
     hipStream_t last_stream = nullptr;
 
@@ -86,9 +87,15 @@ Sched schedule(const vfs_params& p);
 
 // K primal-dual iterations from a warp start with the state parity
 // (base.lc.iu, base.lc.ip); iu, ip receive the parity holding the result.
-// Returns the number of two-iteration launches, which ev0 / ev1 (if given)
-// bracket.
+// Returns the number of multi-iteration passes (pd_pass_iters(base.lc.g,
+// base.lc.n) iterations each), which ev0 / ev1 (if given) bracket.
 int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+// Iterations per pass (2, 3 or 4) of the dominant primal-dual launches of
+// a solve over n pairs of level-0 geometry g.
+int pd_pass_iters(const Geometry& g, int n);
+// Parity change of the state copies (u/v, p/q) over run_pd's K iterations
+// with NP iterations per pass.
+void pd_parity(int K, int NP, int& pu, int& pp);
 
 // PdArgs of a launch with the solver constants of params.
 PdArgs pd_args(const Launch& lc, const vfs_params& params);

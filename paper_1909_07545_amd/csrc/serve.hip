@@ -132,8 +132,10 @@ struct Bucket {
     Slot* slots_dev = nullptr;
     Ctrl* ctrl_dev = nullptr;
     hipStream_t stream = nullptr;
-    hipGraph_t graph[2] = {};
-    hipGraphExec_t exec[2] = {};     // [0] warp step only, [1] every stage
+    // [gl][0]: warp step only, [gl][1]: every stage; gl: the finest level
+    // among the tick's slots (the warp step's grids cover that level)
+    hipGraph_t graph[kMaxLevels][2] = {};
+    hipGraphExec_t exec[kMaxLevels][2] = {};
     int par_u = 0, par_p = 0;       // parity change of one tick's primal-dual launches
     std::vector<SlotState> slot;
     std::deque<Tick> inflight;
@@ -198,8 +200,9 @@ void set_error(vfs_server* sv, vfs_status st, const char* what)
 // One tick of a bucket: the stages every slot may need, selected per slot
 // by its control word (see the comment at the top of this file).  Without
 // `full`, only the warp step (for ticks where no slot starts, changes level
-// or finishes).
-void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int& par_u, int& par_p)
+// or finishes).  The warp step's grids cover level gl, the finest level
+// among the tick's slots.
+void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int gl, int& par_u, int& par_p)
 {
     const vfs_params& P = sv->params;
     const bool tgv = P.reg == VFS_TGV;
@@ -228,21 +231,21 @@ void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int& par_
             // level change: close level + 1, transfer to level
             lc.op = OP_NEWLEVEL;
             lc.dl = 1;
-            lc.gl = 1;
+            lc.gl = gl + 1 < L ? gl + 1 : L - 1;
             launch_linearise(lc, 1, 1, float(P.du_max), st, s);
             lc.dl = 0;
-            lc.gl = 0;
+            lc.gl = gl;
             launch_upsample(lc, tgv ? 1 : 0, st, s);
         }
         lc.op = OP_START;
         lc.gl = L - 1;
         launch_zero_state(lc, tgv ? 1 : 0, st, s);
-        lc.gl = 0;
+        lc.gl = gl;
         lc.op = OP_TENSOR;
         launch_tensor(lc, st, s);
     }
     // warp step
-    lc.gl = 0;
+    lc.gl = gl;
     lc.op = OP_WARP;
     launch_linearise(lc, -1, 0, float(P.du_max), st, s);
     int iu = 0, ip = 0;
@@ -253,6 +256,7 @@ void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int& par_
         lc.ip = ip;
         lc.op = OP_FINISH;
         lc.lev = 0;
+        lc.gl = 0;
         launch_linearise(lc, 1, 1, float(P.du_max), st, s);
         launch_triangulate(lc, s);
     }
@@ -276,21 +280,19 @@ vfs_status make_bucket(vfs_server* sv, const Geometry& g, Bucket*& out)
     CtrlBlock cb{};
     launch_write_ctrl(cb, kMaxBatch, b->ctrl_dev, b->stream);
     if (sv->cfg.use_graphs) {
-        for (int full = 0; full < 2; ++full) {
-            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-                return fail(VFS_E_DEVICE, "hipStreamBeginCapture");
-            enqueue_tick(sv, *b, b->stream, full != 0, b->par_u, b->par_p);
-            if (hipStreamEndCapture(b->stream, &b->graph[full]) != hipSuccess)
-                return fail(VFS_E_DEVICE, "hipStreamEndCapture");
-            if (hipGraphInstantiateWithFlags(&b->exec[full], b->graph[full], 0) != hipSuccess)
-                return fail(VFS_E_DEVICE, "hipGraphInstantiate");
-        }
+        for (int gl = 0; gl < g.L; ++gl)
+            for (int full = 0; full < 2; ++full) {
+                if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                    return fail(VFS_E_DEVICE, "hipStreamBeginCapture");
+                enqueue_tick(sv, *b, b->stream, full != 0, gl, b->par_u, b->par_p);
+                if (hipStreamEndCapture(b->stream, &b->graph[gl][full]) != hipSuccess)
+                    return fail(VFS_E_DEVICE, "hipStreamEndCapture");
+                if (hipGraphInstantiateWithFlags(&b->exec[gl][full], b->graph[gl][full], 0) != hipSuccess)
+                    return fail(VFS_E_DEVICE, "hipGraphInstantiate");
+            }
     } else {
         // parity change of one tick (same launch sequence as the graph)
-        const vfs_params& P = sv->params;
-        const int K = P.iters;
-        const int odd = (K - 1) % 2, pairs = (K - 1 - odd) / 2;
-        b->par_u = b->par_p = (1 + odd + pairs) & 1;
+        pd_parity(sv->params.iters, pd_pass_iters(b->g, b->S), b->par_u, b->par_p);
     }
     if (hipGetLastError() != hipSuccess) return fail(VFS_E_DEVICE, "bucket set-up launch failed");
     out = b.get();
@@ -310,10 +312,11 @@ void bucket_destroy(Bucket& b)
     if (b.stream) (void)hipStreamSynchronize(b.stream);
     for (auto& t : b.inflight) (void)hipEventDestroy(t.ev);
     for (auto e : b.spare_events) (void)hipEventDestroy(e);
-    for (int k = 0; k < 2; ++k) {
-        if (b.exec[k]) (void)hipGraphExecDestroy(b.exec[k]);
-        if (b.graph[k]) (void)hipGraphDestroy(b.graph[k]);
-    }
+    for (int l = 0; l < kMaxLevels; ++l)
+        for (int k = 0; k < 2; ++k) {
+            if (b.exec[l][k]) (void)hipGraphExecDestroy(b.exec[l][k]);
+            if (b.graph[l][k]) (void)hipGraphDestroy(b.graph[l][k]);
+        }
     if (b.slots_dev) (void)hipFree(b.slots_dev);
     if (b.ctrl_dev) (void)hipFree(b.ctrl_dev);
     if (b.stream) (void)hipStreamDestroy(b.stream);
@@ -413,6 +416,7 @@ bool launch_tick(vfs_server* sv, Bucket& b)
     CtrlBlock cb{};
     Tick t;
     bool work = false, full = false;
+    int gl = L - 1;
     for (int z = 0; z < b.S; ++z) {
         SlotState& ss = b.slot[z];
         Ctrl& c = cb.c[z];
@@ -444,17 +448,18 @@ bool launch_tick(vfs_server* sv, Bucket& b)
         c.warp = ss.warp;
         c.ops = ops;
         full |= ops != OP_WARP;
+        if (ss.level < gl) gl = ss.level;
         c.flip = uint8_t(ss.flip);
         work = true;
     }
     if (!work) return false;
     launch_write_ctrl(cb, b.S, b.ctrl_dev, b.stream);
     if (sv->cfg.use_graphs) {
-        if (hipGraphLaunch(b.exec[full ? 1 : 0], b.stream) != hipSuccess)
+        if (hipGraphLaunch(b.exec[gl][full ? 1 : 0], b.stream) != hipSuccess)
             set_error(sv, VFS_E_DEVICE, "hipGraphLaunch failed");
     } else {
         int pu, pp;
-        enqueue_tick(sv, b, b.stream, full, pu, pp);
+        enqueue_tick(sv, b, b.stream, full, gl, pu, pp);
     }
     if (full) ++b.full_ticks;
     if (!b.spare_events.empty()) {
