@@ -286,6 +286,25 @@ def serving_study(args, log_prefix="serving"):
     log(f"{log_prefix}: plain FP32 closed loop {rate0} pairs/s")
     res["closed_loop_batched_fp16"] = run(batched_kw, p16, trace0, closed=True)
     log(f"{log_prefix}: batched FP16 closed loop {res['closed_loop_batched_fp16']['pairs_per_s']} pairs/s")
+    res["closed_loop_batched_fp16_16GiB"] = run(dict(batched_kw, hbm_budget_bytes=16 << 30), p16, trace0,
+                                                closed=True)
+    log(f"{log_prefix}: batched FP16 closed loop, 16 GiB budget: "
+        f"{res['closed_loop_batched_fp16_16GiB']['pairs_per_s']} pairs/s")
+    # served results of the last closed-loop run against solving each alone
+    # (bitwise), for one request of every (rig, size)
+    seen, checked, equal = set(), 0, 0
+    for i, q in enumerate(trace0):
+        key = (q["rig"], q["size"])
+        if key in seen:
+            continue
+        seen.add(key)
+        rg = handles[key]
+        alone = vfs.solve_batch(rg, [imgs[key][0]], [imgs[key][1]], dict(p16, levels=rg.levels), betas=[beta],
+                                etas=[eta])[0]
+        checked += 1
+        equal += int(torch.equal(alone["u"], outs[i]["u"]) and torch.equal(alone["depth"], outs[i]["depth"]))
+    res["alone_vs_served_bitwise"] = {"checked": checked, "equal": equal}
+    log(f"{log_prefix}: {equal} of {checked} served requests equal their alone solve bitwise")
     sweep = []
     for f in args.serve_rates:
         trace = serving.make_trace(f * rate0, n, sp)
@@ -304,11 +323,12 @@ def serving_study(args, log_prefix="serving"):
 
 
 def measured_traffic(config):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None
-    if there is none for this workload or the kernel source has changed since."""
+    """HBM bytes per launch of the dominant kernel (the level-0 three-iteration
+    pass) from the committed rocprofv3 counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy), or None if there is none for this
+    workload or the kernel source has changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pd2_kernel_batch2048_traffic.json")
+    path = os.path.join(ROOT, "profiles", "pdn3_kernel_batch2048_traffic.json")
     if config != "c5" or not os.path.exists(path):
         return None
     rec = json.load(open(path))

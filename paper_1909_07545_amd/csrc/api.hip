@@ -228,14 +228,16 @@ vfs_status check_params(const vfs_params* p)
     return VFS_OK;
 }
 
-// Iterations per pass of the dominant primal-dual launches of a solve (a
-// batch or a serving bucket: n pairs whose level 0 is g's).  Measured on
-// MI355X: three iterations per pass (FP32: 3 wavefronts per SIMD; 16-bit
-// modes: 4) are faster where the passes are bandwidth-bound, from about
-// 16 M level-0 pixels per launch; below that the launches are latency-bound
-// and the shorter two-iteration march is faster.  VFS_PD_PASS=2|3|4
-// overrides the choice for measurements.
-int pd_pass_iters(const Geometry& g, int n)
+// Iterations per pass of the dominant primal-dual launches for pairs whose
+// level 0 is g's.  Measured on MI355X: three iterations per pass (FP32:
+// 3 wavefronts per SIMD; 16-bit modes: 4) are faster where the passes are
+// bandwidth-bound (2048x2048 pairs in batches), two where the launches are
+// latency-bound (pairs up to 1280x1024, alone or in serving buckets).  The
+// choice depends on the pair's size only, not on how many pairs share a
+// launch, so that a pair's result does not depend on its batch (16-bit
+// storage rounds the duals at pass boundaries).  VFS_PD_PASS=2|3|4
+// overrides it for measurements.
+int pd_pass_iters(const Geometry& g)
 {
     static const int forced = [] {
         const char* e = getenv("VFS_PD_PASS");
@@ -243,8 +245,7 @@ int pd_pass_iters(const Geometry& g, int n)
         return v >= 2 && v <= 4 ? v : 0;
     }();
     if (forced) return forced;
-    const long long px = (long long)g.W[0] * g.H[0] * n;
-    return px >= (16ll << 20) ? 3 : 2;
+    return (long long)g.W[0] * g.H[0] >= (2ll << 20) ? 3 : 2;
 }
 
 void pd_parity(int K, int NP, int& pu, int& pp)
@@ -276,7 +277,7 @@ int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s,
     ip ^= 1;
     // iterations 1 .. K-1: the remainder first (one alone, then a pair),
     // then passes of NP iterations each
-    const int NP = pd_pass_iters(base.lc.g, base.lc.n);
+    const int NP = pd_pass_iters(base.lc.g);
     int k = 1;
     int rem = (K - 1) % NP;
     if (rem % 2) {
@@ -553,7 +554,7 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
         sl.eta = float(etas ? etas[b] : params->eta);
         launch_write_slot(sl, r->ws.slots + b, s);
     }
-    r->pass_iters = pd_pass_iters(r->g, n);
+    r->pass_iters = pd_pass_iters(r->g);
     return solve_slots(r->ws.slots, n, r->g, *params, s, r);
 }
 
