@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB device buffer (a plain copy kernel of known size, "
                          "for scaling hardware traffic counters)")
+    ap.add_argument("--pass-iters", type=int, default=0,
+                    help="primal-dual iterations per pass (0: the library's choice by pair size)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving study")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving study (prints its JSON)")
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -80,7 +82,7 @@ def main():
     from synth import configs, scene
 
     cfg = configs.get(args.config)
-    params = configs.solver_params(cfg)
+    params = configs.solver_params(cfg, pass_iters=args.pass_iters)
     rig = scene.make_rig(cfg)
     n = cfg["batch"]
     t0 = time.time()

@@ -78,6 +78,10 @@ typedef struct {
     int reg;                   /* vfs_reg: TGV-L1 of Eq. (10), or TV-L1 (v = 0) */
     double lambda, alpha0, alpha1, beta, eta, du_max, theta_gamma;
     int storage;               /* vfs_storage */
+    int pass_iters;            /* primal-dual iterations per pass over memory of the dominant launches:
+                                  0 = chosen by the library from the pair size (3 from 2 M level-0
+                                  pixels, else 2), or 2, 3, 4; the choice changes only the rounding
+                                  points of 16-bit storage and the speed */
 } vfs_params;
 
 typedef struct vfs_rig vfs_rig;

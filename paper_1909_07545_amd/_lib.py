@@ -34,7 +34,8 @@ class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("warps", ctypes.c_int), ("iters", ctypes.c_int),
                 ("reg", ctypes.c_int), ("lam", ctypes.c_double), ("alpha0", ctypes.c_double),
                 ("alpha1", ctypes.c_double), ("beta", ctypes.c_double), ("eta", ctypes.c_double),
-                ("du_max", ctypes.c_double), ("theta_gamma", ctypes.c_double), ("storage", ctypes.c_int)]
+                ("du_max", ctypes.c_double), ("theta_gamma", ctypes.c_double), ("storage", ctypes.c_int),
+                ("pass_iters", ctypes.c_int)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -123,7 +124,7 @@ def default_params() -> dict:
     _check(lib().vfs_params_default(ctypes.byref(p)))
     return dict(levels=p.levels, warps=p.warps, iters=p.iters, reg="tgv" if p.reg == 0 else "tv",
                 alpha0=p.alpha0, alpha1=p.alpha1, beta=p.beta, eta=p.eta, du_max=p.du_max,
-                theta_gamma=p.theta_gamma, storage=p.storage, **{"lambda": p.lam})
+                theta_gamma=p.theta_gamma, storage=p.storage, pass_iters=p.pass_iters, **{"lambda": p.lam})
 
 
 def _params(d: dict) -> Params:
@@ -131,7 +132,7 @@ def _params(d: dict) -> Params:
     return Params(int(d["levels"]), int(d["warps"]), int(d["iters"]),
                   REGS[reg] if isinstance(reg, str) else int(reg), float(d["lambda"]), float(d["alpha0"]),
                   float(d["alpha1"]), float(d["beta"]), float(d["eta"]), float(d["du_max"]),
-                  float(d.get("theta_gamma", 0.0)), int(d.get("storage", 0)))
+                  float(d.get("theta_gamma", 0.0)), int(d.get("storage", 0)), int(d.get("pass_iters", 0)))
 
 
 def _ptr(t):

@@ -2,7 +2,6 @@
 // level-0 primal-dual timing.  Host code only enqueues work; the solve never
 // waits on the device.
 #include <math.h>
-#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -222,6 +221,8 @@ vfs_status check_params(const vfs_params* p)
     if (p->reg != VFS_TGV && p->reg != VFS_TV) return fail(VFS_E_INVALID, "bad regulariser");
     if (p->storage != VFS_F32 && p->storage != VFS_F16 && p->storage != VFS_BF16)
         return fail(VFS_E_INVALID, "unsupported storage");
+    if (p->pass_iters != 0 && (p->pass_iters < 2 || p->pass_iters > 4))
+        return fail(VFS_E_INVALID, "pass_iters must be 0 (automatic) or 2, 3, 4");
     if (!(p->alpha0 > 0.0) || !(p->alpha1 > 0.0) || !(p->lambda >= 0.0) || !(p->du_max > 0.0) ||
         !(p->theta_gamma >= 0.0) || !(p->beta >= 0.0) || !(p->eta > 0.0))
         return fail(VFS_E_INVALID, "bad solver constants");
@@ -229,22 +230,16 @@ vfs_status check_params(const vfs_params* p)
 }
 
 // Iterations per pass of the dominant primal-dual launches for pairs whose
-// level 0 is g's.  Measured on MI355X: three iterations per pass (FP32:
-// 3 wavefronts per SIMD; 16-bit modes: 4) are faster where the passes are
-// bandwidth-bound (2048x2048 pairs in batches), two where the launches are
-// latency-bound (pairs up to 1280x1024, alone or in serving buckets).  The
-// choice depends on the pair's size only, not on how many pairs share a
-// launch, so that a pair's result does not depend on its batch (16-bit
-// storage rounds the duals at pass boundaries).  VFS_PD_PASS=2|3|4
-// overrides it for measurements.
-int pd_pass_iters(const Geometry& g)
+// level 0 is g's, unless `requested` (2, 3 or 4) fixes it.  Measured on
+// MI355X: three iterations per pass are faster where the passes are
+// bandwidth-bound (2048x2048 pairs: 4 wavefronts per SIMD), two where the
+// launches are latency-bound (pairs up to 1280x1024, alone or in serving
+// buckets).  The choice depends on the pair's size only, not on how many
+// pairs share a launch, so that a pair's result does not depend on its batch
+// (16-bit storage rounds the duals at pass boundaries).
+int pd_pass_iters(const Geometry& g, int requested)
 {
-    static const int forced = [] {
-        const char* e = getenv("VFS_PD_PASS");
-        const int v = e ? atoi(e) : 0;
-        return v >= 2 && v <= 4 ? v : 0;
-    }();
-    if (forced) return forced;
+    if (requested >= 2 && requested <= 4) return requested;
     return (long long)g.W[0] * g.H[0] >= (2ll << 20) ? 3 : 2;
 }
 
@@ -277,7 +272,7 @@ int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s,
     ip ^= 1;
     // iterations 1 .. K-1: the remainder first (one alone, then a pair),
     // then passes of NP iterations each
-    const int NP = pd_pass_iters(base.lc.g);
+    const int NP = base.pass;
     int k = 1;
     int rem = (K - 1) % NP;
     if (rem % 2) {
@@ -345,6 +340,7 @@ PdArgs pd_args(const Launch& lc, const vfs_params& params)
     pa.lambda = float(params.lambda);
     pa.tgv = params.reg == VFS_TGV ? 1 : 0;
     pa.storage = params.storage;
+    pa.pass = pd_pass_iters(lc.g, params.pass_iters);
     return pa;
 }
 
@@ -426,6 +422,7 @@ vfs_status vfs_params_default(vfs_params* out)
     out->du_max = 0.2;
     out->theta_gamma = 0.0;
     out->storage = VFS_F32;
+    out->pass_iters = 0;
     return VFS_OK;
 }
 
@@ -554,7 +551,7 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
         sl.eta = float(etas ? etas[b] : params->eta);
         launch_write_slot(sl, r->ws.slots + b, s);
     }
-    r->pass_iters = pd_pass_iters(r->g);
+    r->pass_iters = pd_pass_iters(r->g, params->pass_iters);
     return solve_slots(r->ws.slots, n, r->g, *params, s, r);
 }
 

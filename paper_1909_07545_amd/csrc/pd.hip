@@ -317,11 +317,19 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
 
     const int r_end = DUAL ? y1 : y1 - 1;       // last row visited (row y1 is the look-ahead)
     // rows are loaded one step ahead of their use, so that a row's memory
-    // latency overlaps the previous row's arithmetic
-    Row nxt = load_row<TGV, PRIMAL, S>(P, x, y0, in_x);
+    // latency overlaps the previous row's arithmetic (the multi-iteration
+    // kernels weigh this against occupancy, see below)
+    constexpr bool PF = true;
+    Row nxt = zero_row();
+    if constexpr (PF) nxt = load_row<TGV, PRIMAL, S>(P, x, y0, in_x);
     for (int r = y0; r <= r_end; ++r) {
-        const Row c = nxt;
-        if (r + 1 <= r_end) nxt = load_row<TGV, PRIMAL, S>(P, x, r + 1, in_x);
+        Row c;
+        if constexpr (PF) {
+            c = nxt;
+            if (r + 1 <= r_end) nxt = load_row<TGV, PRIMAL, S>(P, x, r + 1, in_x);
+        } else {
+            c = load_row<TGV, PRIMAL, S>(P, x, r, in_x);
+        }
         // primal step at row r: x^k from x^{k-1} and y^k
         float un = c.u;
         float2 vn = c.v;
@@ -417,15 +425,21 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
     float2 vb2_m3 = make_float2(0.f, 0.f);
 
     // rows are loaded one step ahead of their use (see pd_kernel)
-    Row nxt = load_row<TGV, true, S>(P, x, y0 - 1, in_x);
+    constexpr bool PF = true;
+    Row nxt = zero_row();
+    if constexpr (PF) nxt = load_row<TGV, true, S>(P, x, y0 - 1, in_x);
     for (int r = y0 - 1; r <= y1 + 2; ++r) {
         // A: iteration-1 primal at row r
         Row c = zero_row();
         float un1 = 0.f, ub1 = 0.f;
         float2 vn1 = make_float2(0.f, 0.f), vb1 = make_float2(0.f, 0.f);
         if (r <= y1 + 1) {
-            c = nxt;
-            if (r + 1 <= y1 + 1) nxt = load_row<TGV, true, S>(P, x, r + 1, in_x);
+            if constexpr (PF) {
+                c = nxt;
+                if (r + 1 <= y1 + 1) nxt = load_row<TGV, true, S>(P, x, r + 1, in_x);
+            } else {
+                c = load_row<TGV, true, S>(P, x, r, in_x);
+            }
             primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, a.tau_scale, un1, vn1);
             ub1 = un1 + a.theta * (un1 - c.u);
             vb1 = make_float2(vn1.x + a.theta * (vn1.x - c.v.x), vn1.y + a.theta * (vn1.y - c.v.y));
@@ -598,12 +612,23 @@ __global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) v
         fD = w.f;
     }
     const int r_lo = y0 - (N - 1), r_hi = y1 + 2 * N - 2, r_load = y1 + N - 1;
-    Row nxt = load_row<TGV, true, S>(P, x, r_lo, in_x);
+    // no prefetch here: its registers would cost a wavefront per SIMD, which
+    // is worth more on the bandwidth-bound grids this kernel serves
+    // (measured).  The choice must not depend on BY: the two march heights
+    // must compile to the same per-pixel arithmetic, so that a pair's result
+    // does not depend on the grid (batch) it runs in.
+    constexpr bool PF = false;
+    Row nxt = zero_row();
+    if constexpr (PF) nxt = load_row<TGV, true, S>(P, x, r_lo, in_x);
     for (int r = r_lo; r <= r_hi; ++r) {
         Row c = zero_row();
         if (r <= r_load) {
-            c = nxt;
-            if (r + 1 <= r_load) nxt = load_row<TGV, true, S>(P, x, r + 1, in_x);
+            if constexpr (PF) {
+                c = nxt;
+                if (r + 1 <= r_load) nxt = load_row<TGV, true, S>(P, x, r + 1, in_x);
+            } else {
+                c = load_row<TGV, true, S>(P, x, r, in_x);
+            }
         }
 #pragma unroll
         for (int d = D - 1; d > 0; --d) {

@@ -87,12 +87,13 @@ Sched schedule(const vfs_params& p);
 
 // K primal-dual iterations from a warp start with the state parity
 // (base.lc.iu, base.lc.ip); iu, ip receive the parity holding the result.
-// Returns the number of multi-iteration passes (pd_pass_iters(base.lc.g)
-// iterations each), which ev0 / ev1 (if given) bracket.
+// Returns the number of multi-iteration passes (base.pass iterations each),
+// which ev0 / ev1 (if given) bracket.
 int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // Iterations per pass (2, 3 or 4) of the dominant primal-dual launches for
-// pairs of level-0 geometry g (independent of the batch).
-int pd_pass_iters(const Geometry& g);
+// pairs of level-0 geometry g (independent of the batch), or `requested` if
+// that is 2, 3 or 4.
+int pd_pass_iters(const Geometry& g, int requested);
 // Parity change of the state copies (u/v, p/q) over run_pd's K iterations
 // with NP iterations per pass.
 void pd_parity(int K, int NP, int& pu, int& pp);

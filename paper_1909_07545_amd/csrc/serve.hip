@@ -292,7 +292,7 @@ vfs_status make_bucket(vfs_server* sv, const Geometry& g, Bucket*& out)
             }
     } else {
         // parity change of one tick (same launch sequence as the graph)
-        pd_parity(sv->params.iters, pd_pass_iters(b->g), b->par_u, b->par_p);
+        pd_parity(sv->params.iters, pd_pass_iters(b->g, sv->params.pass_iters), b->par_u, b->par_p);
     }
     if (hipGetLastError() != hipSuccess) return fail(VFS_E_DEVICE, "bucket set-up launch failed");
     out = b.get();

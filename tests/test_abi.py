@@ -41,7 +41,7 @@ def test_params_default_are_the_paper_values(vfs):
     d = vfs.default_params()
     assert (d["alpha0"], d["alpha1"], d["beta"], d["eta"], d["du_max"]) == \
         (g["alpha0"], g["alpha1"], g["beta"], g["eta"], g["du_max_px"])
-    assert d["reg"] == "tgv" and d["theta_gamma"] == 0.0
+    assert d["reg"] == "tgv" and d["theta_gamma"] == 0.0 and d["pass_iters"] == 0
 
 
 CAM = dict(model="kb", width=64, height=48, fx=20.0, fy=20.0, cx=31.5, cy=23.5, k=(0.01, -0.005, 0.0, 0.0),
@@ -83,6 +83,11 @@ def test_solve_and_steps_reject_bad_arguments(vfs):
     bad = vfs._params(dict(vfs.default_params(), alpha1=0.0))
     assert L.vfs_step_pd(8, 8, 8, one, one, one, one, one, one, one, one, one, one, one, ctypes.byref(bad), 3,
                          None) == -1
+    for npass in (1, 5, -2):
+        badp = vfs._params(dict(vfs.default_params(), pass_iters=npass))
+        assert L.vfs_step_pd(8, 8, 8, one, one, one, one, one, one, one, one, one, one, one, ctypes.byref(badp),
+                             3, None) == -1
+        assert "pass_iters" in L.vfs_last_error().decode()
     assert L.vfs_step_upsample(4, 4, 2, one, one, one, 8, one, one, None) == -1
     assert L.vfs_profile_enable(None, 1) == -1
 

@@ -168,19 +168,25 @@ def _pd_state(cid, level, tgv=True, seed=5):
     return flags, T, Iu, rho, u, v, p.astype(np.float32), q.astype(np.float32)
 
 
-@pytest.mark.parametrize("cid,level,K,reg,tg", [
-    ("c1", 0, 1, "tgv", 0.0), ("c1", 0, 2, "tgv", 0.0), ("c1", 0, 3, "tgv", 0.0), ("r200", 0, 4, "tv", 0.0),
-    ("c1", 0, 50, "tgv", 0.0), ("c5", 0, 5, "tgv", 0.0), ("r200", 1, 6, "tgv", 0.4),
-    ("r200", 0, 7, "tgv", 0.0), ("r200", 0, 50, "tv", 0.0), ("c1", 1, 30, "tgv", 0.3),
-    ("c2", 0, 20, "tgv", 0.0), ("c5", 0, 3, "tgv", 0.0)])
-def test_primal_dual(vfs, cid, level, K, reg, tg):
+@pytest.mark.parametrize("cid,level,K,reg,tg,npass", [
+    ("c1", 0, 1, "tgv", 0.0, 0), ("c1", 0, 2, "tgv", 0.0, 0), ("c1", 0, 3, "tgv", 0.0, 0),
+    ("r200", 0, 4, "tv", 0.0, 0), ("c1", 0, 50, "tgv", 0.0, 0), ("c5", 0, 5, "tgv", 0.0, 0),
+    ("r200", 1, 6, "tgv", 0.4, 0), ("r200", 0, 7, "tgv", 0.0, 0), ("r200", 0, 50, "tv", 0.0, 0),
+    ("c1", 1, 30, "tgv", 0.3, 0), ("c2", 0, 20, "tgv", 0.0, 0), ("c5", 0, 3, "tgv", 0.0, 0),
+    ("c1", 0, 50, "tgv", 0.0, 3), ("r200", 0, 8, "tv", 0.0, 3), ("r200", 1, 11, "tgv", 0.4, 3),
+    ("c5", 0, 8, "tgv", 0.0, 3), ("c1", 0, 50, "tgv", 0.0, 4), ("r200", 0, 9, "tgv", 0.0, 4),
+    ("r200", 0, 6, "tv", 0.0, 4), ("c2", 0, 14, "tgv", 0.0, 4), ("c5", 0, 6, "tgv", 0.0, 2)])
+def test_primal_dual(vfs, cid, level, K, reg, tg, npass):
     """K iterations of Eq. (11) from a warp start: u, v, p, q within 2e-5 of
-    the FP64 oracle (float32 accumulates ~1e-7 per iteration)."""
+    the FP64 oracle (float32 accumulates ~1e-7 per iteration).  npass: the
+    iterations per pass of the multi-iteration launches (0: the library's
+    choice, 3 on the 2048x2048 level, 2 elsewhere), so that the 2-, 3- and
+    4-iteration kernels all run, with every remainder of K - 1."""
     import torch
     tgv = reg == "tgv"
     flags, T, Iu, rho, u, v, p, q = _pd_state(cid, level, tgv)
     H, W = u.shape
-    params = dict(configs.PAPER_PARAMS, levels=1, warps=1, iters=K, reg=reg, theta_gamma=tg)
+    params = dict(configs.PAPER_PARAMS, levels=1, warps=1, iters=K, reg=reg, theta_gamma=tg, pass_iters=npass)
     tpack = np.concatenate([T, Iu[..., None]], -1).astype(np.float32)
     tu, tp = _t(u), _t(p)
     tv, tq = (_t(v), _t(q)) if tgv else (None, None)
