@@ -48,17 +48,30 @@ typedef enum {
     VFS_E_DEVICE = -6       /* a HIP runtime call failed */
 } vfs_status;
 
-typedef enum { VFS_PINHOLE = 0, VFS_EQUIDISTANT = 1, VFS_KANNALA_BRANDT = 2 } vfs_model;
+typedef enum {
+    VFS_PINHOLE = 0,
+    VFS_EQUIDISTANT = 1,
+    VFS_KANNALA_BRANDT = 2,
+    VFS_UNIFIED = 3,            /* k[0] = xi */
+    VFS_ENHANCED_UNIFIED = 4    /* k[0] = alpha, k[1] = beta */
+} vfs_model;
 typedef enum { VFS_TGV = 0, VFS_TV = 1 } vfs_reg;
 /* Storage of the dual variables and of the tensor pack (T^(1/2) of Eq. (12)
  * and I_u): 32-bit float, IEEE half or bfloat16; every update is computed in
  * FP32 and u, v, rho_c stay FP32 (rho_c is formed from I_u as stored). */
 typedef enum { VFS_F32 = 0, VFS_F16 = 1, VFS_BF16 = 2 } vfs_storage;
 
-/* Camera: r_d(theta) = theta + k1 theta^3 + k2 theta^5 + k3 theta^7 +
- * k4 theta^9 (Kannala-Brandt; equidistant is k = 0; pinhole r_d = tan theta),
- * pixel = (cx, cy) + (fx, fy) r_d (cos phi, sin phi).  fov_deg is the full
- * field of view of the circular mask of Sec. IV-B. */
+/* Camera (Sec. III-B: any model with a defined projection; Sec. III-D names
+ * the unified and enhanced unified models for their closed-form inverse):
+ * pixel = (cx, cy) + (fx, fy) r_d(theta) (cos phi, sin phi) for a ray at
+ * angle theta from the axis and azimuth phi, with
+ *   Kannala-Brandt  r_d = theta + k1 theta^3 + k2 theta^5 + k3 theta^7 + k4 theta^9
+ *                   (equidistant is k = 0; pinhole r_d = tan theta),
+ *   unified         r_d = sin theta / (xi + cos theta)            (k[0] = xi >= 0),
+ *   enh. unified    r_d = sin theta / (alpha sqrt(beta sin^2 theta + cos^2 theta)
+ *                                      + (1 - alpha) cos theta)   (k[0] = alpha in [0, 1], k[1] = beta > 0).
+ * fov_deg is the full field of view of the circular mask of Sec. IV-B; the
+ * radial map must be defined and increasing up to half of it. */
 typedef struct {
     int model;             /* vfs_model */
     int width, height;

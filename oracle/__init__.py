@@ -13,7 +13,12 @@ oracle itself; the tests named live in ``tests/``):
 
 * ``project`` / ``unproject`` -- round trip pi(pi^-1(x)) = x, equidistant
   closed form theta = r/f, Kannala-Brandt with k = 0 equals equidistant,
-  pinhole closed form (test_oracle_geometry).
+  pinhole closed form (test_oracle_geometry).  Unified and enhanced unified
+  models: xi = 0 / alpha = 0 equal the pinhole, the enhanced model with
+  beta = 1 equals the unified one with xi = alpha / (1 - alpha), the radial
+  projection and the closed-form inverse round-trip, agreement with the
+  renderer's Newton-inverted camera, angle limits acos(-1/xi) / acos(-xi),
+  tangency to the brute-force epipolar curve (test_oracle_unified).
 * ``trajectory_field`` -- tangency to the brute-force epipolar curve traced by
   projecting points at 400 depths along back-projected rays; exact (+1, 0)
   for a pinhole with x-translation; radial field for z-translation;
@@ -51,7 +56,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vfs_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2, "kannala_brandt": 2}
+MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2, "kannala_brandt": 2, "unified": 3, "ucm": 3,
+          "eucm": 4, "enhanced_unified": 4}
 REGS = {"tgv": 0, "tv": 1}
 
 

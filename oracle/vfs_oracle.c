@@ -30,15 +30,16 @@
 
 #define OR_PI 3.14159265358979323846
 
-enum { OR_PINHOLE = 0, OR_EQUIDISTANT = 1, OR_KANNALA_BRANDT = 2 };
+enum { OR_PINHOLE = 0, OR_EQUIDISTANT = 1, OR_KANNALA_BRANDT = 2, OR_UNIFIED = 3, OR_EUCM = 4 };
 enum { OR_TGV = 0, OR_TV = 1 };
 enum { OR_OK = 0, OR_E_INVALID = -1, OR_E_MODEL = -4, OR_E_DEGENERATE = -5 };
 
 typedef struct {
-    int model;          /* OR_PINHOLE, OR_EQUIDISTANT, OR_KANNALA_BRANDT */
+    int model;          /* OR_PINHOLE, OR_EQUIDISTANT, OR_KANNALA_BRANDT, OR_UNIFIED, OR_EUCM */
     int width, height;
     double fx, fy, cx, cy;
-    double k[4];        /* Kannala-Brandt k1..k4 (ignored otherwise) */
+    double k[4];        /* Kannala-Brandt k1..k4; unified: k[0] = xi; enhanced unified: k[0] = alpha,
+                           k[1] = beta (ignored otherwise) */
     double fov_deg;     /* full field of view of the circular mask */
 } or_camera;
 
@@ -49,15 +50,35 @@ typedef struct {
 
 /* ------------------------------------------------------------------------ */
 /* Camera models.  The method needs only a defined projection pi and, for   */
-/* depth, its inverse (Sec. III-B; Sec. III-D last paragraph).  Kannala-    */
-/* Brandt: r_d = theta + k1 theta^3 + k2 theta^5 + k3 theta^7 + k4 theta^9  */
-/* (equidistant is k = 0, pinhole is r_d = tan theta).                       */
+/* depth, its inverse (Sec. III-B; Sec. III-D last paragraph, which names    */
+/* the unified and enhanced unified models as ones with a closed-form        */
+/* inverse).  Every model here is radially symmetric: a ray at angle theta   */
+/* from the axis lands at normalised radius r_d(theta).                      */
+/*  Kannala-Brandt: r_d = theta + k1 theta^3 + k2 theta^5 + k3 theta^7 +     */
+/*    k4 theta^9 (equidistant is k = 0, pinhole is r_d = tan theta).         */
+/*  Unified (xi): the point is projected from the centre of a unit sphere    */
+/*    moved by xi along the axis, m = (x, y) / (xi |X| + z), so               */
+/*    r_d = sin theta / (xi + cos theta)  (xi = 0 is the pinhole).           */
+/*  Enhanced unified (alpha, beta): m = (x, y) / (alpha rho + (1 - alpha) z), */
+/*    rho = sqrt(beta (x^2 + y^2) + z^2), so                                  */
+/*    r_d = sin theta / (alpha sqrt(beta sin^2 + cos^2) + (1 - alpha) cos)    */
+/*    (alpha = 0 is the pinhole; beta = 1 is the unified model with           */
+/*    xi = alpha / (1 - alpha) and focal length scaled by 1 / (1 - alpha)).   */
 /* ------------------------------------------------------------------------ */
+
+/* Denominator of the unified models' radial map (> 0 where it is defined). */
+static double or_unified_den(const or_camera *c, double th)
+{
+    double s = sin(th), co = cos(th);
+    if (c->model == OR_UNIFIED) return c->k[0] + co;
+    return c->k[0] * sqrt(c->k[1] * s * s + co * co) + (1.0 - c->k[0]) * co;
+}
 
 static double or_theta_d(const or_camera *c, double th)
 {
     if (c->model == OR_PINHOLE) return tan(th);
     if (c->model == OR_EQUIDISTANT) return th;
+    if (c->model == OR_UNIFIED || c->model == OR_EUCM) return sin(th) / or_unified_den(c, th);
     double t3 = th * th * th, t5 = t3 * th * th, t7 = t5 * th * th, t9 = t7 * th * th;
     return th + c->k[0] * t3 + c->k[1] * t5 + c->k[2] * t7 + c->k[3] * t9;
 }
@@ -66,6 +87,17 @@ static double or_dtheta_d(const or_camera *c, double th)
 {
     if (c->model == OR_PINHOLE) { double cs = cos(th); return 1.0 / (cs * cs); }
     if (c->model == OR_EQUIDISTANT) return 1.0;
+    if (c->model == OR_UNIFIED || c->model == OR_EUCM) {
+        /* quotient rule on sin / D */
+        double s = sin(th), co = cos(th), D = or_unified_den(c, th), dD;
+        if (c->model == OR_UNIFIED) {
+            dD = -s;
+        } else {
+            double a = c->k[0], b = c->k[1], g = sqrt(b * s * s + co * co);
+            dD = a * (b - 1.0) * s * co / g - (1.0 - a) * s;
+        }
+        return (co * D - s * dD) / (D * D);
+    }
     double t2 = th * th, t4 = t2 * t2, t6 = t4 * t2, t8 = t4 * t4;
     return 1.0 + 3.0 * c->k[0] * t2 + 5.0 * c->k[1] * t4 + 7.0 * c->k[2] * t6 + 9.0 * c->k[3] * t8;
 }
@@ -77,8 +109,10 @@ double or_theta_limit(const or_camera *c)
 {
     if (c->model == OR_PINHOLE) return 0.5 * OR_PI * (1.0 - 1e-9);
     if (c->model == OR_EQUIDISTANT) return OR_PI;
+    int unified = c->model == OR_UNIFIED || c->model == OR_EUCM;
     for (int i = 1; i <= 4096; ++i) {
         double th = OR_PI * (double)i / 4096.0;
+        if (unified && !(or_unified_den(c, th) > 0.0)) return OR_PI * (double)(i - 1) / 4096.0;
         if (!(or_dtheta_d(c, th) > 0.0)) return OR_PI * (double)(i - 1) / 4096.0;
     }
     return OR_PI;
@@ -128,13 +162,44 @@ static int or_project(const or_camera *c, const double X[3], double x[2])
     return 1;
 }
 
-/* pi^-1: pixel -> unit ray in the camera frame. */
+/* pi^-1: pixel -> unit ray in the camera frame.  The unified models use
+ * their closed forms: unified, the ray (lambda m, lambda - xi) with lambda =
+ * (xi + sqrt(1 + (1 - xi^2) r^2)) / (1 + r^2), which has unit length;
+ * enhanced unified, normalise(m, m_z) with m_z = (1 - beta alpha^2 r^2) /
+ * (alpha sqrt(1 - (2 alpha - 1) beta r^2) + 1 - alpha).  Beyond the angle
+ * limit the radius is clamped to r_d(th_lim), as for the other models. */
 static void or_unproject(const or_camera *c, double th_lim, double px, double py, double r[3])
 {
     double mx = (px - c->cx) / c->fx, my = (py - c->cy) / c->fy;
     if (c->model == OR_PINHOLE) {
         double n = sqrt(mx * mx + my * my + 1.0);
         r[0] = mx / n; r[1] = my / n; r[2] = 1.0 / n;
+        return;
+    }
+    if (c->model == OR_UNIFIED || c->model == OR_EUCM) {
+        double rr = sqrt(mx * mx + my * my);
+        if (th_lim < OR_PI) {
+            double rmax = or_theta_d(c, th_lim);
+            if (rr > rmax) {
+                mx *= rmax / rr;
+                my *= rmax / rr;
+                rr = rmax;
+            }
+        }
+        double r2 = rr * rr, X[3];
+        if (c->model == OR_UNIFIED) {
+            double xi = c->k[0];
+            double disc = 1.0 + (1.0 - xi * xi) * r2;
+            double lam = (xi + sqrt(disc > 0.0 ? disc : 0.0)) / (1.0 + r2);
+            X[0] = lam * mx; X[1] = lam * my; X[2] = lam - xi;
+        } else {
+            double a = c->k[0], b = c->k[1];
+            double disc = 1.0 - (2.0 * a - 1.0) * b * r2;
+            X[0] = mx; X[1] = my;
+            X[2] = (1.0 - b * a * a * r2) / (a * sqrt(disc > 0.0 ? disc : 0.0) + 1.0 - a);
+        }
+        double n = sqrt(X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+        r[0] = X[0] / n; r[1] = X[1] / n; r[2] = X[2] / n;
         return;
     }
     double rd = sqrt(mx * mx + my * my);
@@ -163,12 +228,14 @@ static or_camera or_level_camera(const or_camera *c, int l)
 int or_camera_check(const or_camera *c)
 {
     if (c->width <= 0 || c->height <= 0 || !(c->fx > 0.0) || !(c->fy > 0.0)) return OR_E_INVALID;
-    if (c->model < OR_PINHOLE || c->model > OR_KANNALA_BRANDT) return OR_E_INVALID;
+    if (c->model < OR_PINHOLE || c->model > OR_EUCM) return OR_E_INVALID;
+    if (c->model == OR_UNIFIED && !(c->k[0] >= 0.0)) return OR_E_INVALID;
+    if (c->model == OR_EUCM && !(c->k[0] >= 0.0 && c->k[0] <= 1.0 && c->k[1] > 0.0)) return OR_E_INVALID;
     double half = 0.5 * c->fov_deg * OR_PI / 180.0;
     if (!(half > 0.0)) return OR_E_INVALID;
     if (c->model == OR_PINHOLE && !(half < 0.5 * OR_PI)) return OR_E_MODEL;
     if (half > OR_PI) return OR_E_MODEL;
-    if (c->model == OR_KANNALA_BRANDT && or_theta_limit(c) < half) return OR_E_MODEL;
+    if (c->model >= OR_KANNALA_BRANDT && or_theta_limit(c) < half) return OR_E_MODEL;
     return OR_OK;
 }
 

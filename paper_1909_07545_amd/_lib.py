@@ -12,7 +12,8 @@ LIB_PATH = os.path.join(_HERE, "libvfs.so")
 
 FIELD_TRAJECTORY, FIELD_CALIBRATION, FIELD_FLAGS = 0, 1, 2
 F_MASK, F_MX, F_MY, F_DATA, F_EPI = 1, 2, 4, 8, 16
-MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2, "kannala_brandt": 2}
+MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2, "kannala_brandt": 2, "unified": 3, "ucm": 3,
+          "eucm": 4, "enhanced_unified": 4}
 REGS = {"tgv": 0, "tv": 1}
 STATUS = {0: "VFS_OK", -1: "VFS_E_INVALID", -2: "VFS_E_NOMEM", -3: "VFS_E_BUDGET", -4: "VFS_E_MODEL",
           -5: "VFS_E_DEGENERATE", -6: "VFS_E_DEVICE"}

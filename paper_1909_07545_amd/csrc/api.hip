@@ -36,16 +36,20 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// Largest angle of the grid i*pi/4096 up to which the radial map increases.
+// Largest angle of the grid i*pi/4096 up to which the radial map is defined
+// (unified models: positive denominator) and increases.
 double theta_limit(const vfs_camera& c)
 {
     if (c.model == VFS_PINHOLE) return 0.5 * kPi * (1.0 - 1e-9);
     if (c.model == VFS_EQUIDISTANT) return kPi;
     Cam t{};
-    t.model = 2;
+    t.model = c.model;
     for (int a = 0; a < 4; ++a) t.k[a] = c.k[a];
-    for (int i = 1; i <= 4096; ++i)
-        if (!(cam_drd(t, kPi * i / 4096.0) > 0.0)) return kPi * (i - 1) / 4096.0;
+    for (int i = 1; i <= 4096; ++i) {
+        const double th = kPi * i / 4096.0;
+        if (t.model >= VFS_UNIFIED && !(cam_uden(t, th) > 0.0)) return kPi * (i - 1) / 4096.0;
+        if (!(cam_drd(t, th) > 0.0)) return kPi * (i - 1) / 4096.0;
+    }
     return kPi;
 }
 
@@ -54,13 +58,16 @@ vfs_status check_camera(const vfs_camera* c, const char* name)
     if (!c) return fail(VFS_E_INVALID, "%s is NULL", name);
     if (c->width <= 0 || c->height <= 0 || !(c->fx > 0.0) || !(c->fy > 0.0))
         return fail(VFS_E_INVALID, "%s: bad size or focal length", name);
-    if (c->model < VFS_PINHOLE || c->model > VFS_KANNALA_BRANDT) return fail(VFS_E_INVALID, "%s: bad model", name);
+    if (c->model < VFS_PINHOLE || c->model > VFS_ENHANCED_UNIFIED) return fail(VFS_E_INVALID, "%s: bad model", name);
+    if (c->model == VFS_UNIFIED && !(c->k[0] >= 0.0)) return fail(VFS_E_INVALID, "%s: unified model needs xi >= 0", name);
+    if (c->model == VFS_ENHANCED_UNIFIED && !(c->k[0] >= 0.0 && c->k[0] <= 1.0 && c->k[1] > 0.0))
+        return fail(VFS_E_INVALID, "%s: enhanced unified model needs 0 <= alpha <= 1, beta > 0", name);
     const double half = 0.5 * c->fov_deg * kPi / 180.0;
     if (!(half > 0.0)) return fail(VFS_E_INVALID, "%s: field of view must be positive", name);
     if (c->model == VFS_PINHOLE && !(half < 0.5 * kPi))
         return fail(VFS_E_MODEL, "%s: pinhole field of view must be below 180 degrees", name);
     if (half > kPi) return fail(VFS_E_MODEL, "%s: field of view above 360 degrees", name);
-    if (c->model == VFS_KANNALA_BRANDT && theta_limit(*c) < half)
+    if (c->model >= VFS_KANNALA_BRANDT && theta_limit(*c) < half)
         return fail(VFS_E_MODEL, "%s: radial map not increasing up to half the field of view", name);
     return VFS_OK;
 }
@@ -72,7 +79,7 @@ Cam to_cam(const vfs_camera& c)
     o.width = c.width;
     o.height = c.height;
     o.fx = c.fx; o.fy = c.fy; o.cx = c.cx; o.cy = c.cy;
-    for (int a = 0; a < 4; ++a) o.k[a] = c.model == VFS_KANNALA_BRANDT ? c.k[a] : 0.0;
+    for (int a = 0; a < 4; ++a) o.k[a] = c.model >= VFS_KANNALA_BRANDT ? c.k[a] : 0.0;
     o.th_lim = theta_limit(c);
     return o;
 }

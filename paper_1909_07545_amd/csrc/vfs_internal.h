@@ -21,20 +21,36 @@ constexpr int kMaxLevels = 12;
 constexpr int kMaxBatch = 32;
 
 // ----------------------------------------------------------------- camera
-// Kannala-Brandt radial map r_d(theta) = theta + k1 theta^3 + k2 theta^5 +
-// k3 theta^7 + k4 theta^9; equidistant is k = 0, pinhole r_d = tan(theta).
+// Radially symmetric models: a ray at angle theta from the axis lands at
+// normalised radius r_d(theta).
+//   Kannala-Brandt: r_d = theta + k1 theta^3 + k2 theta^5 + k3 theta^7 +
+//     k4 theta^9 (equidistant is k = 0; pinhole r_d = tan(theta)).
+//   Unified (xi = k[0]): projection from the centre of a unit sphere moved
+//     by xi along the axis, r_d = sin / (xi + cos).
+//   Enhanced unified (alpha = k[0], beta = k[1]):
+//     r_d = sin / (alpha sqrt(beta sin^2 + cos^2) + (1 - alpha) cos).
+// The unified models invert in closed form; Kannala-Brandt by Newton.
 struct Cam {
-    int model;          // 0 pinhole, 1 equidistant, 2 Kannala-Brandt
+    int model;          // 0 pinhole, 1 equidistant, 2 Kannala-Brandt, 3 unified, 4 enhanced unified
     int width, height;
     double fx, fy, cx, cy;
     double k[4];
     double th_lim;      // the radial map is inverted on [0, th_lim] and saturates beyond
 };
 
+// Denominator of the unified models' radial map.
+__host__ __device__ inline double cam_uden(const Cam& c, double th)
+{
+    const double s = sin(th), co = cos(th);
+    if (c.model == 3) return c.k[0] + co;
+    return c.k[0] * sqrt(c.k[1] * s * s + co * co) + (1.0 - c.k[0]) * co;
+}
+
 __host__ __device__ inline double cam_rd(const Cam& c, double th)
 {
     if (c.model == 0) return tan(th);
     if (c.model == 1) return th;
+    if (c.model >= 3) return sin(th) / cam_uden(c, th);
     const double t2 = th * th;
     return th * (1.0 + t2 * (c.k[0] + t2 * (c.k[1] + t2 * (c.k[2] + t2 * c.k[3]))));
 }
@@ -43,17 +59,41 @@ __host__ __device__ inline double cam_drd(const Cam& c, double th)
 {
     if (c.model == 0) { const double cs = cos(th); return 1.0 / (cs * cs); }
     if (c.model == 1) return 1.0;
+    if (c.model >= 3) {
+        const double s = sin(th), co = cos(th), D = cam_uden(c, th);
+        double dD = -s;
+        if (c.model == 4) {
+            const double g = sqrt(c.k[1] * s * s + co * co);
+            dD = c.k[0] * (c.k[1] - 1.0) * s * co / g - (1.0 - c.k[0]) * s;
+        }
+        return (co * D - s * dD) / (D * D);
+    }
     const double t2 = th * th;
     return 1.0 + t2 * (3.0 * c.k[0] + t2 * (5.0 * c.k[1] + t2 * (7.0 * c.k[2] + t2 * 9.0 * c.k[3])));
 }
 
-// Inverse of the radial map: bracketed Newton on [0, th_lim].
+// Inverse of the radial map: closed form for the unified models (the angle
+// of their back-projected ray), bracketed Newton on [0, th_lim] otherwise.
 __host__ __device__ inline double cam_theta(const Cam& c, double rd)
 {
     if (!(rd > 0.0)) return 0.0;
     if (c.model == 0) return atan(rd);
     if (c.model == 1) return rd < c.th_lim ? rd : c.th_lim;
     if (rd >= cam_rd(c, c.th_lim)) return c.th_lim;
+    if (c.model == 3) {
+        // back-projected ray (lambda m, lambda - xi), lambda = (xi + sqrt(1 + (1 - xi^2) r^2)) / (1 + r^2)
+        const double xi = c.k[0], r2 = rd * rd;
+        const double disc = 1.0 + (1.0 - xi * xi) * r2;
+        const double lam = (xi + sqrt(disc > 0.0 ? disc : 0.0)) / (1.0 + r2);
+        return atan2(lam * rd, lam - xi);
+    }
+    if (c.model == 4) {
+        // back-projected ray (m, m_z), m_z = (1 - beta alpha^2 r^2) / (alpha sqrt(1 - (2 alpha - 1) beta r^2) + 1 - alpha)
+        const double a = c.k[0], b = c.k[1], r2 = rd * rd;
+        const double disc = 1.0 - (2.0 * a - 1.0) * b * r2;
+        const double mz = (1.0 - b * a * a * r2) / (a * sqrt(disc > 0.0 ? disc : 0.0) + 1.0 - a);
+        return atan2(rd, mz);
+    }
     double lo = 0.0, hi = c.th_lim, th = rd < c.th_lim ? rd : 0.5 * c.th_lim;
     for (int it = 0; it < 200; ++it) {
         const double f = cam_rd(c, th) - rd;

@@ -66,6 +66,16 @@ CONFIGS = {
                depth_range=(0.5, 20.0), tex_k=(0.5, 8.0), levels=7, warps=15, iters=200,
                batch=8, supersample=1, per_pair_tensor=True, beta_range=(6.0, 12.0),
                eta_range=(0.7, 1.0)),
+    # unified (xi = 1.2, from the paper's list of models with a closed-form
+    # inverse) and enhanced unified (alpha 0.62, beta 1.1) rigs, 200 degrees
+    "ucm": _cfg("ucm", seed_offset=12, name="unified320", width=320, height=240, model="unified",
+                model_params=(1.2, 0.0, 0.0, 0.0), f=None, fov_deg=200.0, kb_range=0.0, baseline=0.08,
+                rot_deg=2.5, scene="room", depth_range=(1.0, 10.0), tex_k=(0.5, 8.0), levels=3, warps=4,
+                iters=30, supersample=2),
+    "eucm": _cfg("eucm", seed_offset=13, name="eunified320", width=320, height=240, model="eucm",
+                 model_params=(0.62, 1.1, 0.0, 0.0), f=None, fov_deg=200.0, kb_range=0.0, baseline=0.08,
+                 rot_deg=2.5, scene="room", depth_range=(1.0, 10.0), tex_k=(0.5, 8.0), levels=3, warps=4,
+                 iters=30, supersample=2),
     "r200": _cfg("r200", seed_offset=11, name="ragged200", width=200, height=136, model="kb",
                  f=None, fov_deg=185.0, kb_range=0.05, baseline=0.08, rot_deg=3.0, scene="room",
                  depth_range=(1.0, 10.0), tex_k=(0.5, 8.0), levels=3, warps=4, iters=30),

@@ -58,6 +58,33 @@ def _kcoef(cam):
     return tuple(cam.get("k", (0.0,) * 4)) if cam["model"] == "kb" else (0.0, 0.0, 0.0, 0.0)
 
 
+UNIFIED = ("unified", "eucm")
+
+
+def _urd(cam, th):
+    """Radial map of the unified (xi) and enhanced unified (alpha, beta)
+    models from their projections: m = (x, y) / (xi |X| + z) and
+    m = (x, y) / (alpha sqrt(beta (x^2 + y^2) + z^2) + (1 - alpha) z),
+    evaluated for the unit ray at angle th (torch or numpy)."""
+    lib = torch if isinstance(th, torch.Tensor) else np
+    s, c = lib.sin(th), lib.cos(th)
+    k = cam["k"]
+    if cam["model"] == "unified":
+        return s / (k[0] + c)
+    return s / (k[0] * lib.sqrt(k[1] * s * s + c * c) + (1.0 - k[0]) * c)
+
+
+def _uth_max(cam):
+    """Largest angle (on a fine grid) up to which the unified radial map is
+    defined and increasing."""
+    th = np.linspace(0.0, np.pi, 200_001)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = _urd(cam, th)
+    ok = np.isfinite(r) & (r >= 0) & np.concatenate([[True], np.diff(r) > 0])
+    bad = np.nonzero(~ok)[0]
+    return th[bad[0] - 1] if len(bad) else np.pi
+
+
 def cam_rays(cam, px, py):
     """Unit rays (..., 3) and polar angles of pixel coordinates (Newton on the radial map)."""
     mx = (px - cam["cx"]) / cam["fx"]
@@ -66,6 +93,21 @@ def cam_rays(cam, px, py):
     if cam["model"] == "pinhole":
         n = torch.sqrt(mx * mx + my * my + 1.0)
         return torch.stack([mx / n, my / n, 1.0 / n], -1), torch.atan(rd)
+    if cam["model"] in UNIFIED:
+        # Newton with a central-difference slope, on [0, the invertible range]
+        tmax = _uth_max(cam)
+        th = torch.clamp(torch.atan(rd), max=tmax)
+        h = 1e-7
+        for _ in range(80):
+            d = (_urd(cam, th + h) - _urd(cam, th - h)) / (2 * h)
+            d = torch.where(d.abs() > 1e-9, d, torch.full_like(d, 1e-9))
+            nt = torch.clamp(th - (_urd(cam, th) - rd) / d, 0.0, tmax)
+            done = float((nt - th).abs().max()) < 1e-15
+            th = nt
+            if done:
+                break
+        s = torch.where(rd > 0, torch.sin(th) / torch.where(rd > 0, rd, torch.ones_like(rd)), torch.ones_like(rd))
+        return torch.stack([s * mx, s * my, torch.cos(th)], -1), th
     k = _kcoef(cam)
     th = torch.clamp(rd, max=np.pi)
     if any(k):
@@ -88,7 +130,7 @@ def cam_project(cam, X):
         return torch.stack([cam["cx"] + cam["fx"] * X[..., 0] / X[..., 2],
                             cam["cy"] + cam["fy"] * X[..., 1] / X[..., 2]], -1)
     th = torch.atan2(rho, X[..., 2])
-    rd = _rd(_kcoef(cam), th)
+    rd = _urd(cam, th) if cam["model"] in UNIFIED else _rd(_kcoef(cam), th)
     sr = torch.where(rho > 0, rd / torch.where(rho > 0, rho, torch.ones_like(rho)), torch.zeros_like(rho))
     return torch.stack([cam["cx"] + cam["fx"] * sr * X[..., 0], cam["cy"] + cam["fy"] * sr * X[..., 1]], -1)
 
@@ -123,8 +165,11 @@ def sample_kb(rng, kr, fov_deg, min_slope=0.2):
 
 def make_camera(model, W, H, f, fov_deg, k=(0.0, 0.0, 0.0, 0.0)):
     if f is None:
-        kk = k if model == "kb" else (0.0, 0.0, 0.0, 0.0)
-        f = (min(W, H) / 2.0) / _np_rd(kk, np.deg2rad(fov_deg) / 2)
+        if model in UNIFIED:
+            rd = float(_urd(dict(model=model, k=k), np.deg2rad(fov_deg) / 2))
+        else:
+            rd = _np_rd(k if model == "kb" else (0.0, 0.0, 0.0, 0.0), np.deg2rad(fov_deg) / 2)
+        f = (min(W, H) / 2.0) / rd
     return dict(model=model, width=int(W), height=int(H), fx=float(f), fy=float(f),
                 cx=(W - 1) / 2.0, cy=(H - 1) / 2.0, k=tuple(float(x) for x in k),
                 fov_deg=float(fov_deg))
@@ -134,7 +179,12 @@ def make_rig(cfg, rng=None):
     """Camera pair and relative pose (X1 = R X0 + t) of a configuration."""
     if rng is None:
         rng = np.random.default_rng(np.random.SeedSequence(cfg["seed"]).spawn(4)[0])
-    k = sample_kb(rng, cfg["kb_range"], cfg["fov_deg"]) if cfg["model"] == "kb" else np.zeros(4)
+    if cfg["model"] == "kb":
+        k = sample_kb(rng, cfg["kb_range"], cfg["fov_deg"])
+    elif cfg["model"] in UNIFIED:
+        k = np.asarray(cfg["model_params"], np.float64)
+    else:
+        k = np.zeros(4)
     cam = make_camera(cfg["model"], cfg["width"], cfg["height"], cfg.get("f"), cfg["fov_deg"], k)
     axis = rng.normal(size=3)
     R = _rotation(axis, cfg["rot_deg"]) if cfg["rot_deg"] else np.eye(3)
