@@ -1,7 +1,7 @@
 """Ablation of the warping schedule on rendered scenes with ground truth (a
 script, not collected by pytest; it needs a GPU).
 
-  python -m tests.ablation_study OUT.json [--pairs P]
+  python -m tests.ablation_study OUT.json [--pairs P] [--noise SIGMA]
 
 Reproduces the shape of the paper's timing / accuracy trade-off (Sec. IV-C:
 error against the number of warps N at a 0.2 px clip, time against N; error
@@ -11,7 +11,8 @@ for every pixel inside the level-0 mask whose data term is on and whose
 scene point camera 1 sees, the endpoint error of the recovered
 correspondence x + w against the rendered one (in the pre-rotated frame),
 and the share of pixels whose error exceeds 1 px and 5 px.  Time is the GPU
-time of one whole solve (median of 3).
+time of one whole solve (median of 3).  --noise sets the Gaussian noise of
+the renders (default: the configuration's 0.01).
 """
 from __future__ import annotations
 
@@ -38,6 +39,8 @@ def main():
     out_path = sys.argv[1]
     pairs = int(sys.argv[sys.argv.index("--pairs") + 1]) if "--pairs" in sys.argv else 4
     cfg = configs.get("c2")
+    if "--noise" in sys.argv:
+        cfg["noise"] = float(sys.argv[sys.argv.index("--noise") + 1])
     rig = scene.make_rig(cfg)
     R = vfs.Rig(rig["cam0"], rig["cam1"], rig["R"], rig["t"], cfg["levels"])
     flags = R.field(0, vfs.FIELD_FLAGS).cpu().numpy()
@@ -69,8 +72,8 @@ def main():
                 "tau5_pct": round(100 * float(np.mean(e > 5.0)), 2), "epe_median": round(float(np.median(e)), 4),
                 "ms_per_solve": round(1e3 * float(np.mean(times)), 2)}
 
-    res = {"workload": f"c2: {pairs} rendered 640x480 KB rooms, {cfg['levels']} levels, {cfg['iters']} iterations "
-                       f"per warp, FP32 TGV-L1, lambda {configs.PAPER_PARAMS['lambda']}",
+    res = {"workload": f"c2: {pairs} rendered 640x480 KB rooms (noise sigma {cfg['noise']}), {cfg['levels']} levels, "
+                       f"{cfg['iters']} iterations per warp, FP32 TGV-L1, lambda {configs.PAPER_PARAMS['lambda']}",
            "by_warps": [], "by_clip": []}
     for n in range(1, 21):
         r = run(n, 0.2)
