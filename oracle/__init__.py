@@ -38,9 +38,17 @@ oracle itself; the tests named live in ``tests/``):
   of the linearised energy (subdifferential of Eq. (10), written from the
   energy, not from the iteration); energy decreases over each inner loop
   (test_oracle_solver).
+* ``linearise`` -- the warped tangent is unit length and radial away from
+  the epipole of a radial field, goes to zero approaching it and is
+  Lipschitz across it (test_oracle_solver).
+* ``rank_transform`` -- equals its definition written out in plain loops,
+  ties included; invariant under strictly increasing intensity maps and
+  transposition (test_oracle_rank).
 * ``solve`` -- pinhole camera with x-translation equals an independently
   written rectified 1-D TGV-L1 solver; recovered depth of a rendered plane
-  and room matches the renderer's ground truth (test_oracle_solver).
+  and room matches the renderer's ground truth (test_oracle_solver).  With
+  the rank data term on the plane: unaffected by a tone-curve change of I1
+  that breaks brightness constancy (test_oracle_rank).
 * ``triangulate`` -- ground-truth correspondences recover the renderer's
   range; pinhole rectified case gives Z = f b / disparity (test_oracle_geometry).
 """
@@ -59,6 +67,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2, "kannala_brandt": 2, "unified": 3, "ucm": 3,
           "eucm": 4, "enhanced_unified": 4}
 REGS = {"tgv": 0, "tv": 1}
+DATA_TERMS = {"brightness": 0, "rank": 1}
 
 
 class _Camera(ctypes.Structure):
@@ -71,7 +80,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("warps", ctypes.c_int), ("iters", ctypes.c_int),
                 ("reg", ctypes.c_int), ("lam", ctypes.c_double), ("alpha0", ctypes.c_double),
                 ("alpha1", ctypes.c_double), ("beta", ctypes.c_double), ("eta", ctypes.c_double),
-                ("du_max", ctypes.c_double), ("theta_gamma", ctypes.c_double)]
+                ("du_max", ctypes.c_double), ("theta_gamma", ctypes.c_double), ("data_term", ctypes.c_int)]
 
 
 def build(force: bool = True) -> str:
@@ -113,7 +122,9 @@ def _par(p: dict) -> _Params:
     return _Params(int(p["levels"]), int(p["warps"]), int(p["iters"]),
                    REGS[reg] if isinstance(reg, str) else int(reg), float(p["lambda"]),
                    float(p["alpha0"]), float(p["alpha1"]), float(p["beta"]), float(p["eta"]),
-                   float(p["du_max"]), float(p.get("theta_gamma", 0.0)))
+                   float(p["du_max"]), float(p.get("theta_gamma", 0.0)),
+                   DATA_TERMS[p.get("data_term", 0)] if isinstance(p.get("data_term", 0), str)
+                   else int(p.get("data_term", 0)))
 
 
 def _d(a):
@@ -276,6 +287,17 @@ def steps(T, mask, alpha0: float, alpha1: float, reg="tgv"):
     lib().or_steps(_p(T), _p(mask), W, H, ctypes.c_double(alpha0), ctypes.c_double(alpha1),
                    REGS[reg] if isinstance(reg, str) else int(reg), _p(sp), _p(tu), _p(tv))
     return sp, tu, tv
+
+
+def rank_transform(I, radius: int = 2):
+    """Share of the (2r+1)^2 - 1 neighbours strictly darker than each pixel
+    (edge-clamped neighbourhood): the data term's image for data_term
+    "rank"."""
+    I = _d(I)
+    H, W = I.shape
+    out = np.zeros((H, W))
+    lib().or_rank_transform(_p(I), W, H, int(radius), _p(out))
+    return out
 
 
 def project_balls(phi, n: int):

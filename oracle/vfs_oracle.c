@@ -46,6 +46,7 @@ typedef struct {
 typedef struct {
     int levels, warps, iters, reg;
     double lambda, alpha0, alpha1, beta, eta, du_max, theta_gamma;
+    int data_term;      /* 0: brightness, 1: rank transform of radius 2 (census variant) */
 } or_params;
 
 /* ------------------------------------------------------------------------ */
@@ -326,6 +327,35 @@ static double or_bilinear(const double *I, int W, int H, double x, double y)
 }
 
 /* Pre-rotation warp, done once per pair: I1'(x) = I1(x + c(x)). */
+/* ------------------------------------------------------------------------ */
+/* Rank transform (a census variant; the paper allows any image I in its     */
+/* data term, Sec. III-A, and mentions census matching among the rectified   */
+/* comparisons): the share of the (2r+1)^2 - 1 neighbours of a pixel that    */
+/* are strictly darker than it, neighbours outside the image taken at the    */
+/* nearest edge pixel.  Any strictly increasing change of the intensities    */
+/* leaves it unchanged.                                                      */
+/* ------------------------------------------------------------------------ */
+
+void or_rank_transform(const double *I, int W, int H, int r, double *out)
+{
+    const double n = (double)((2 * r + 1) * (2 * r + 1) - 1);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            const double c = I[(size_t)i * W + j];
+            int count = 0;
+            for (int di = -r; di <= r; ++di)
+                for (int dj = -r; dj <= r; ++dj) {
+                    if (!di && !dj) continue;
+                    int y = i + di, x = j + dj;
+                    y = y < 0 ? 0 : (y >= H ? H - 1 : y);
+                    x = x < 0 ? 0 : (x >= W ? W - 1 : x);
+                    count += I[(size_t)y * W + x] < c;
+                }
+            out[(size_t)i * W + j] = count / n;
+        }
+}
+
 void or_prerotate(const double *I1, int W, int H, const double *cf, double *out)
 {
 #pragma omp parallel for schedule(static)
@@ -730,8 +760,12 @@ void or_pd_iterations(int W, int H, const or_params *pp, const double *T, const 
 
 /* ------------------------------------------------------------------------ */
 /* Warping (Sec. III-A, Eqs. (3), (5); Sec. III-B; Algorithm 1).             */
-/* At the warped point y = x + w the tangent gamma'_w is the renormalised    */
-/* bicubic (Keys, a = -1/2, clamp-to-edge) sample of the trajectory field;   */
+/* At the warped point y = x + w the tangent gamma'_w is the bicubic (Keys, */
+/* a = -1/2, clamp-to-edge) sample g of the trajectory field divided by     */
+/* max(|g|, 1/2): unit length wherever the sample is at least half a unit   */
+/* long, shorter only where its taps reach an epipole, around which the    */
+/* tangents turn through every direction (Sec. III-B) and a unit            */
+/* renormalisation of the short sum would be discontinuous in y;            */
 /* I_u = I1(y + gamma'_w) - I1(y) is a forward difference of one pixel       */
 /* along it (Eq. (5)); rho_c = I1(y) - I0(x) - u_w I_u.  The data term is   */
 /* off (I_u = rho_c = 0) where dvalid is 0 (outside the mask, outside       */
@@ -785,7 +819,9 @@ void or_linearise(int W, int H, const double *J0, const double *J1, const double
             u_w[idx] = u[idx];
             or_bicubic2(gamma, W, H, yx, yy, g);
             double n = sqrt(g[0] * g[0] + g[1] * g[1]);
-            if (n > 0.0) { g[0] /= n; g[1] /= n; } else { g[0] = 0.0; g[1] = 0.0; }
+            if (n < 0.5) n = 0.5;
+            g[0] /= n;
+            g[1] /= n;
             gamma_w[2 * idx] = g[0];
             gamma_w[2 * idx + 1] = g[1];
             if (!dvalid[idx]) { Iu[idx] = 0.0; rho[idx] = 0.0; continue; }
@@ -912,6 +948,7 @@ int or_solve(const or_camera *c0, const or_camera *c1, const double R[9], const 
 {
     int W = c0->width, H = c0->height, L = pp->levels;
     if (L < 1 || pp->warps < 0 || pp->iters < 0) return OR_E_INVALID;
+    if (pp->data_term != 0 && pp->data_term != 1) return OR_E_INVALID;
     if (c1->width != W || c1->height != H) return OR_E_INVALID;
     if ((W % (1 << (L - 1))) || (H % (1 << (L - 1)))) return OR_E_INVALID;
     int st = or_camera_check(c0);
@@ -951,6 +988,8 @@ int or_solve(const or_camera *c0, const or_camera *c1, const double R[9], const 
     double *gam = malloc(2 * n0 * sizeof(double));
     unsigned char *ml = malloc(n0), *dl = malloc(n0), *el = malloc(n0), *mprev = malloc(n0);
     unsigned char *dv0 = malloc(n0);
+    double *R0 = pp->data_term == 1 ? malloc(n0 * sizeof(double)) : NULL;
+    double *R1 = pp->data_term == 1 ? malloc(n0 * sizeof(double)) : NULL;
     size_t lvl_off = 0;
     for (int l = 0; l < L - 1; ++l) lvl_off += (size_t)(W >> l) * (H >> l);
 
@@ -965,6 +1004,13 @@ int or_solve(const or_camera *c0, const or_camera *c1, const double R[9], const 
         for (size_t i = 0; i < nl; ++i) dl[i] = ml[i] && dl[i] && !el[i];
         if (l == 0) memcpy(dv0, dl, n0);
         or_tensor(J0[l], ml, Wl, Hl, pp->beta, pp->eta, T);
+        if (R0) {
+            /* rank data term: the linearisation of this level sees the
+               rank transforms of the level's images; the tensor keeps the
+               intensities */
+            or_rank_transform(J0[l], Wl, Hl, 2, R0);
+            or_rank_transform(J1[l], Wl, Hl, 2, R1);
+        }
         or_steps(T, ml, Wl, Hl, pp->alpha0, pp->alpha1, pp->reg, sp, tu, tv);
         if (l == L - 1) {
             memset(u, 0, nl * sizeof(double));
@@ -976,7 +1022,7 @@ int or_solve(const or_camera *c0, const or_camera *c1, const double R[9], const 
         memset(p, 0, 2 * nl * sizeof(double));
         memset(q, 0, 4 * nl * sizeof(double));
         for (int ww = 0; ww < pp->warps; ++ww) {
-            or_linearise(Wl, Hl, J0[l], J1[l], gam, dl, u, w, uw, gw, Iu, rho);
+            or_linearise(Wl, Hl, R0 ? R0 : J0[l], R0 ? R1 : J1[l], gam, dl, u, w, uw, gw, Iu, rho);
             memcpy(ubar, u, nl * sizeof(double));
             memcpy(vbar, v, 2 * nl * sizeof(double));
             or_pd_iterations(Wl, Hl, pp, T, ml, sp, tu, tv, Iu, rho, u, ubar, v, vbar, p, q, pp->iters, NULL);
@@ -997,6 +1043,8 @@ int or_solve(const or_camera *c0, const or_camera *c1, const double R[9], const 
         or_triangulate(c0, R, t, w, dv0, depth, Z, valid);
     }
 
+    free(R0);
+    free(R1);
     for (int l = 0; l < L; ++l) { free(J0[l]); free(J1[l]); }
     free(J0); free(J1); free(m0); free(vc); free(d0); free(cf);
     free(u); free(w); free(uc); free(wc); free(ubar); free(v); free(vbar); free(p); free(q); free(T);

@@ -15,6 +15,7 @@ F_MASK, F_MX, F_MY, F_DATA, F_EPI = 1, 2, 4, 8, 16
 MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2, "kannala_brandt": 2, "unified": 3, "ucm": 3,
           "eucm": 4, "enhanced_unified": 4}
 REGS = {"tgv": 0, "tv": 1}
+DATA_TERMS = {"brightness": 0, "rank": 1}
 STATUS = {0: "VFS_OK", -1: "VFS_E_INVALID", -2: "VFS_E_NOMEM", -3: "VFS_E_BUDGET", -4: "VFS_E_MODEL",
           -5: "VFS_E_DEGENERATE", -6: "VFS_E_DEVICE"}
 
@@ -36,7 +37,7 @@ class Params(ctypes.Structure):
                 ("reg", ctypes.c_int), ("lam", ctypes.c_double), ("alpha0", ctypes.c_double),
                 ("alpha1", ctypes.c_double), ("beta", ctypes.c_double), ("eta", ctypes.c_double),
                 ("du_max", ctypes.c_double), ("theta_gamma", ctypes.c_double), ("storage", ctypes.c_int),
-                ("pass_iters", ctypes.c_int)]
+                ("pass_iters", ctypes.c_int), ("data_term", ctypes.c_int)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -84,6 +85,7 @@ def lib():
         L.vfs_profile_enable.argtypes = [_vp, ctypes.c_int]
         L.vfs_profile_read.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int]
         L.vfs_params_default.argtypes = [_vp]
+        L.vfs_step_rank.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
         L.vfs_step_energy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t] + [_vp] * 7 + [_vp]
         L.vfs_step_pd_energy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t] + [_vp] * 11 + \
             [_vp, ctypes.c_int, _vp, _vp]
@@ -125,7 +127,8 @@ def default_params() -> dict:
     _check(lib().vfs_params_default(ctypes.byref(p)))
     return dict(levels=p.levels, warps=p.warps, iters=p.iters, reg="tgv" if p.reg == 0 else "tv",
                 alpha0=p.alpha0, alpha1=p.alpha1, beta=p.beta, eta=p.eta, du_max=p.du_max,
-                theta_gamma=p.theta_gamma, storage=p.storage, pass_iters=p.pass_iters, **{"lambda": p.lam})
+                theta_gamma=p.theta_gamma, storage=p.storage, pass_iters=p.pass_iters,
+                data_term="rank" if p.data_term == 1 else "brightness", **{"lambda": p.lam})
 
 
 def _params(d: dict) -> Params:
@@ -133,7 +136,8 @@ def _params(d: dict) -> Params:
     return Params(int(d["levels"]), int(d["warps"]), int(d["iters"]),
                   REGS[reg] if isinstance(reg, str) else int(reg), float(d["lambda"]), float(d["alpha0"]),
                   float(d["alpha1"]), float(d["beta"]), float(d["eta"]), float(d["du_max"]),
-                  float(d.get("theta_gamma", 0.0)), int(d.get("storage", 0)), int(d.get("pass_iters", 0)))
+                  float(d.get("theta_gamma", 0.0)), int(d.get("storage", 0)), int(d.get("pass_iters", 0)),
+                  DATA_TERMS[dt] if isinstance(dt := d.get("data_term", 0), str) else int(dt))
 
 
 def _ptr(t):
@@ -238,6 +242,12 @@ def step_pd(tpack, rho, flags, u, v, p, q, params: dict, iters: int, stream=None
     _check(lib().vfs_step_pd(W, H, W, _ptr(tpack), _ptr(rho), _ptr(flags), _ptr(u), _ptr(v), _ptr(p), _ptr(q),
                              _ptr(su), _ptr(sv), _ptr(sp), _ptr(sq), ctypes.byref(pp), int(iters),
                              _stream(stream)))
+
+
+def step_rank(I0, I1, R0, R1, stream=None):
+    """Rank transforms of two (H, W) planes into R0, R1 (vfs_step_rank)."""
+    H, W = I0.shape
+    _check(lib().vfs_step_rank(W, H, W, _ptr(I0), _ptr(I1), _ptr(R0), _ptr(R1), _stream(stream)))
 
 
 def step_energy(tpack, rho, flags, u, v, params: dict, stream=None) -> float:

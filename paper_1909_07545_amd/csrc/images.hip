@@ -144,9 +144,11 @@ __global__ void tensor_kernel(Launch lc)
     st4<S>(sl.tpack, (size_t)i * pitch + j, t);
 }
 
-// clip < 0: clip when the slot's warp index is > 0 (serving ticks).
+// clip < 0: clip when the slot's warp index is > 0 (serving ticks).  rank:
+// the data term compares the level's rank transforms R0, R1 instead of the
+// images themselves (the tensor keeps the intensities).
 template <int S>
-__global__ void linearise_kernel(Launch lc, int clip, int clip_only, float du_max)
+__global__ void linearise_kernel(Launch lc, int clip, int clip_only, float du_max, int rank)
 {
     Pick pk;
     int j, i;
@@ -173,19 +175,25 @@ __global__ void linearise_kernel(Launch lc, int clip, int clip_only, float du_ma
     }
     if (clip_only) return;
     sl.uw[o] = uu;
-    // tangent at the warped point (bicubic sample of the trajectory field, renormalised)
+    // Tangent at the warped point: the bicubic sample of the trajectory field
+    // over max(|sample|, 1/2).  Samples shorter than 1/2 only occur where the
+    // taps reach an epipole (the field turns through every direction around
+    // it); scaling them by 2 instead of to unit length keeps gamma_w a
+    // continuous function of the warped point there.
     float2 g = bicubic2(sl.gamma[l], pitch, W, H, j, i, ww.x, ww.y);
-    const float n = sqrtf(g.x * g.x + g.y * g.y);
-    if (n > 0.f) { g.x /= n; g.y /= n; } else { g.x = 0.f; g.y = 0.f; }
+    const float n = fmaxf(sqrtf(g.x * g.x + g.y * g.y), 0.5f);
+    g.x /= n;
+    g.y /= n;
     sl.gw[o] = g;
     float Iu = 0.f, rc = 0.f;
     if (sl.flags[l][o] & F_DATA) {
-        const float* J1 = sl.J1 + off;
+        const float* J1 = rank ? sl.R1 : sl.J1 + off;
+        const float i0 = rank ? sl.R0[o] : sl.J0[os];
         const float i1 = bilinear(J1, pitch, W, H, j, i, ww.x, ww.y);
         const float i1s = bilinear(J1, pitch, W, H, j, i, ww.x + g.x, ww.y + g.y);
         // rho_c is formed from I_u as stored, so that rho_c + u I_u is exact at u = u_w
         Iu = as_stored<S>(i1s - i1);
-        rc = i1 - sl.J0[os] - uu * Iu;
+        rc = i1 - i0 - uu * Iu;
     }
     if constexpr (S == ST_F32) {
         static_cast<float4*>(sl.tpack)[o].w = Iu;
@@ -195,6 +203,35 @@ __global__ void linearise_kernel(Launch lc, int clip, int clip_only, float du_ma
         st4<S>(sl.tpack, o, t);
     }
     sl.rho[o] = rc;
+}
+
+// Rank transform (a census variant): the share of the 5x5 neighbours that are
+// strictly darker than the pixel, neighbours outside the level taken at the
+// nearest edge pixel.  Counts are exact, so the result is that of any
+// correct implementation on the same float inputs.
+__global__ void rank_kernel(Launch lc)
+{
+    Pick pk;
+    int j, i;
+    if (!pixel_of(lc, pk, j, i)) return;
+    const Slot& sl = lc.slots[blockIdx.z];
+    const int l = pk.l, W = lc.g.W[l], H = lc.g.H[l], pitch = lc.g.pitch[l];
+    const long long off = lc.g.off[l];
+    constexpr int r = kRankRadius;
+    constexpr float norm = 1.f / float((2 * r + 1) * (2 * r + 1) - 1);
+    const float* img[2] = {sl.J0 + off, sl.J1 + off};
+    float* out[2] = {sl.R0, sl.R1};
+    for (int k = 0; k < 2; ++k) {
+        const float* I = img[k];
+        const float c = I[(size_t)i * pitch + j];
+        int count = 0;
+        for (int di = -r; di <= r; ++di) {
+            const float* row = I + (size_t)clampi(i + di, 0, H - 1) * pitch;
+            for (int dj = -r; dj <= r; ++dj)
+                if (di || dj) count += row[clampi(j + dj, 0, W - 1)] < c;
+        }
+        out[k][(size_t)i * pitch + j] = float(count) * norm;
+    }
 }
 
 // Level l + 1 -> level l (Sec. IV-B): u doubled, w doubled (bilinear over the
@@ -347,10 +384,16 @@ void launch_tensor(const Launch& lc, int storage, hipStream_t s)
     VFS_BY_STORAGE(storage, hipLaunchKernelGGL(tensor_kernel<S>, grid_for(lc), dim3(64), 0, s, lc));
 }
 
-void launch_linearise(const Launch& lc, int clip, int clip_only, float du_max, int storage, hipStream_t s)
+void launch_linearise(const Launch& lc, int clip, int clip_only, float du_max, int rank, int storage,
+                      hipStream_t s)
 {
     VFS_BY_STORAGE(storage, hipLaunchKernelGGL(linearise_kernel<S>, grid_for(lc), dim3(64), 0, s, lc, clip,
-                                               clip_only, du_max));
+                                               clip_only, du_max, rank));
+}
+
+void launch_rank(const Launch& lc, hipStream_t s)
+{
+    hipLaunchKernelGGL(rank_kernel, grid_for(lc), dim3(64), 0, s, lc);
 }
 
 void launch_upsample(const Launch& lc, int tgv, int storage, hipStream_t s)

@@ -24,12 +24,12 @@ inline size_t stacked_elems(const Geometry& g) { return size_t(g.off[g.L - 1]) +
 
 // Byte offsets of one pair's solve state inside its region (256-byte aligned).
 struct PairLayout {
-    size_t J0, J1, u[2], v[2], p[2], q[2], w, uw, gw, tpack, rho;
+    size_t J0, J1, u[2], v[2], p[2], q[2], w, uw, gw, tpack, rho, R0, R1;
     size_t bytes;
     int storage;
-    bool tgv;
+    bool tgv, rank;
 };
-PairLayout make_layout(const Geometry& g, int storage, bool tgv);
+PairLayout make_layout(const Geometry& g, int storage, bool tgv, bool rank);
 // Points the state fields of sl into region (device memory of lay.bytes).
 void bind_state(Slot& sl, void* region, const PairLayout& lay);
 
@@ -47,7 +47,7 @@ struct Workspace {
     ~Workspace() { release(); }
     void release();
 };
-vfs_status ensure_workspace(Workspace& ws, const Geometry& g, int n, int storage, bool tgv);
+vfs_status ensure_workspace(Workspace& ws, const Geometry& g, int n, int storage, bool tgv, bool rank);
 
 }  // namespace vfs
 

@@ -13,6 +13,14 @@ by pytest; it needs a GPU and a few minutes of host CPU).
       levels 4 / 5 / 5): one pair per (size, rig 0 / 1) served by the FP16
       continuous-batching server and by the plain FP32 server, against the
       oracle.
+
+  python -m tests.accuracy_study data_term OUT.json
+      Brightness-constancy against rank-transform data term on rendered
+      scenes with ground truth (the 128x128 plane, 4 pairs of the 640x480
+      Kannala-Brandt room): unchanged images, I1 through a strictly
+      increasing intensity curve, and I1 under a radial gain (vignetting of
+      camera 1 only).  Error of x + w against the rendered correspondence
+      over pixels whose data term is on and that camera 1 sees.
 """
 from __future__ import annotations
 
@@ -124,9 +132,59 @@ def serving():
     return {"serving_accuracy": rows}
 
 
+def data_term():
+    import numpy as np
+    import torch
+
+    import paper_1909_07545_amd as vfs
+    from synth import configs, scene
+
+    def curve(I, cam):
+        return 1.25 * I + 0.03 + 0.1 * np.tanh(3.0 * I)
+
+    def vignette(I, cam):
+        H, W = I.shape
+        jj, ii = np.meshgrid(np.arange(W), np.arange(H))
+        r2 = ((jj - cam["cx"]) ** 2 + (ii - cam["cy"]) ** 2) / (0.25 * (W * W + H * H))
+        return I * (1.0 - 0.45 * r2)
+
+    changes = {"none": None, "curve": curve, "vignette": vignette}
+    terms = [("brightness", configs.PAPER_PARAMS["lambda"])] + [("rank", lam) for lam in (2.0, 5.0, 15.0, 30.0)]
+    rows = []
+    for cid, pairs in (("c1", 1), ("c2", 4)):
+        cfg = configs.get(cid)
+        rig = scene.make_rig(cfg)
+        R = vfs.Rig(rig["cam0"], rig["cam1"], rig["R"], rig["t"], cfg["levels"])
+        flags = R.field(0, vfs.FIELD_FLAGS).cpu().numpy()
+        data_on = (flags & vfs.F_DATA) != 0
+        scenes = []
+        for b in range(pairs):
+            I0, I1, gt = scene.render_pair(rig, cfg, b, with_gt=True)
+            scenes.append((I0, I1, gt["flow"], data_on & gt["visible"]))
+        log(f"data term: {cid} {pairs} pairs rendered")
+        for cname, ch in changes.items():
+            for term, lam in terms:
+                params = configs.solver_params(cfg, data_term=term, **{"lambda": lam})
+                errs = []
+                for I0, I1, flow, keep in scenes:
+                    I1c = I1 if ch is None else ch(I1.astype(np.float64), rig["cam1"]).astype(np.float32)
+                    o = vfs.solve(R, torch.from_numpy(I0).cuda(), torch.from_numpy(np.ascontiguousarray(I1c)).cuda(),
+                                  params)
+                    errs.append(np.linalg.norm(o["w"].cpu().numpy() - flow, axis=-1)[keep])
+                e = np.concatenate(errs)
+                row = {"config": cid, "change": cname, "data_term": term, "lambda": lam,
+                       "tau1_pct": round(100 * float(np.mean(e > 1.0)), 2),
+                       "tau5_pct": round(100 * float(np.mean(e > 5.0)), 2),
+                       "epe_median": round(float(np.median(e)), 4)}
+                rows.append(row)
+                log(f"data term: {json.dumps(row)}")
+    return {"workload": "c1: 128x128 equidistant plane, 1 pair; c2: 640x480 KB room, 4 pairs; schedules of the "
+                        "configurations, FP32 TGV-L1", "rows": rows}
+
+
 def main():
     what, out = sys.argv[1], sys.argv[2]
-    res = precision() if what == "precision" else serving()
+    res = {"precision": precision, "serving": serving, "data_term": data_term}[what]()
     with open(out, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res), flush=True)

@@ -41,8 +41,8 @@ def workload():
     return dict(rigs=handles, imgs=imgs)
 
 
-def _params(iters, storage):
-    return configs.solver_params(dict(levels=1, warps=3, iters=iters), storage=storage)
+def _params(iters, storage, data_term="brightness"):
+    return configs.solver_params(dict(levels=1, warps=3, iters=iters), storage=storage, data_term=data_term)
 
 
 def _requests(n, seed):
@@ -102,10 +102,11 @@ def _assert_equal(a, b, tag):
         assert torch.equal(a[k], b[k]), (tag, k, (a[k].float() - b[k].float()).abs().nan_to_num(0).max().item())
 
 
-@pytest.mark.parametrize("iters,storage", [(4, 1), (5, 1), (6, 1), (4, 0), (5, 0)])
-def test_mix_equals_alone(workload, iters, storage):
+@pytest.mark.parametrize("iters,storage,data_term", [(4, 1, "brightness"), (5, 1, "brightness"), (6, 1, "brightness"),
+                                                     (4, 0, "brightness"), (5, 0, "brightness"), (5, 1, "rank")])
+def test_mix_equals_alone(workload, iters, storage, data_term):
     import paper_1909_07545_amd as vfs
-    params = _params(iters, storage)
+    params = _params(iters, storage, data_term)
     reqs = _requests(12, 100 + iters + 10 * storage)
     outs, tickets, t_sub, stats, times = _serve(vfs, workload, reqs, params, waves=3, max_slots=4)
     for i, req in enumerate(reqs):

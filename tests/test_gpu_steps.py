@@ -153,6 +153,25 @@ def test_linearise_and_clip(vfs, cid, level):
     assert np.max(np.abs(_np(rho) - rhoo)) < 5e-5
 
 
+@pytest.mark.parametrize("H,W", [(128, 128), (136, 200), (1, 7), (3, 2), (2048, 2048)])
+def test_rank(vfs, H, W):
+    """The rank transform (5x5, share of strictly darker neighbours, edges
+    clamped): the neighbour counts are integers decided by float32
+    comparisons on both sides, so they must match exactly; random values
+    and a quantised image full of ties."""
+    import torch
+    rng = np.random.default_rng(H * 7 + W)
+    I0 = _smooth_image(H, W, 11) if min(H, W) > 8 else rng.random((H, W)).astype(np.float32)
+    I1 = (np.round(rng.random((H, W)) * 5) / 5).astype(np.float32)
+    R0 = torch.full((H, W), float("nan"), device="cuda")
+    R1 = torch.full((H, W), float("nan"), device="cuda")
+    vfs.step_rank(_t(I0), _t(I1), R0, R1)
+    for got, I in ((R0, I0), (R1, I1)):
+        g = _np(got).astype(np.float64) * 24.0
+        assert np.array_equal(np.rint(g), np.rint(oracle.rank_transform(f32(I), 2) * 24.0))
+        assert np.max(np.abs(g - np.rint(g))) < 1e-5
+
+
 def _pd_state(cid, level, tgv=True, seed=5):
     rig, flags, J0, _, _ = _level_inputs(cid, level, seed=seed)
     H, W = J0.shape

@@ -177,6 +177,53 @@ def test_clip_special_case():
     assert np.array_equal(st["u"], out["u"])
 
 
+def test_warped_tangent_is_continuous_at_an_epipole():
+    """Around an epipole the trajectory field turns through every direction
+    (Sec. III-B), and its sample there is a short sum of opposed vectors.  The
+    warped tangent is that sample over max(|sample|, 1/2): unit length where
+    the bicubic taps stay away from the epipole, 0 at the epipole itself, and
+    tending to 0 as the warped point approaches it (a unit renormalisation
+    would jump there)."""
+    H, W, e = 20, 24, (11.0, 8.0)
+    jj, ii = np.meshgrid(np.arange(W, dtype=float), np.arange(H, dtype=float))
+    r = np.stack([jj - e[0], ii - e[1]], -1)
+    n = np.linalg.norm(r, axis=-1, keepdims=True)
+    gam = np.where(n > 0, r / np.where(n > 0, n, 1.0), 0.0)
+    Z = np.zeros((H, W))
+
+    def tangent(points):
+        w = np.zeros((H, W, 2))
+        w[..., 0] = points[..., 0] - jj
+        w[..., 1] = points[..., 1] - ii
+        _, gw, _, _ = oracle.linearise(Z, Z, gam, np.zeros((H, W), np.uint8), Z, w)
+        return gw
+
+    # far from the epipole: unit length, and within the interpolation error of the radial direction
+    far = (np.abs(jj - e[0]) >= 4) | (np.abs(ii - e[1]) >= 4)
+    pts = np.stack([jj + 0.37, ii + 0.61], -1)
+    g = tangent(pts)
+    assert np.max(np.abs(np.linalg.norm(g, axis=-1)[far] - 1.0)) < 1e-12
+    rad = (pts - np.array(e)) / np.linalg.norm(pts - np.array(e), axis=-1, keepdims=True)
+    assert np.min(np.sum(g * rad, axis=-1)[far]) > 0.99
+    # at the epipole and approaching it along several directions
+    for d in ((1.0, 0.0), (0.6, -0.8), (-0.28, 0.96)):
+        prev = None
+        for delta in (1e-2, 1e-4, 1e-6, 1e-9, 0.0):
+            p = np.broadcast_to(np.array([e[0] + delta * d[0], e[1] + delta * d[1]]), (H, W, 2)).copy()
+            length = float(np.linalg.norm(tangent(p)[0, 0]))
+            assert length <= 40.0 * delta + 1e-15, (d, delta, length)
+            prev = length
+        assert prev == 0.0
+    # Lipschitz in the warped point on a fine grid across the epipole
+    xs = e[0] + np.linspace(-2.5, 2.5, W)
+    ys = e[1] + np.linspace(-2.5, 2.5, H)
+    gx, gy = np.meshgrid(xs, ys)
+    g = tangent(np.stack([gx, gy], -1))
+    h = xs[1] - xs[0]
+    assert np.max(np.linalg.norm(np.diff(g, axis=1), axis=-1)) / h < 6.0
+    assert np.max(np.linalg.norm(np.diff(g, axis=0), axis=-1)) / (ys[1] - ys[0]) < 6.0
+
+
 def test_pinhole_x_translation_equals_rectified_solver():
     """Pinhole with pure x-translation reduces to the conventional (1, 0)
     rectified search: the oracle's whole loop equals an independently written
