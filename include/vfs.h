@@ -253,6 +253,44 @@ vfs_status vfs_diff_stats(int width, int height, size_t pitch, const float* a, c
                           const uint8_t* flags, double* mean_abs, double* max_abs, long long* count,
                           void* hip_stream);
 
+/* ---- Rectification, for comparison with a rectified pipeline (Sec. V-A
+ * runs the same energy on images rectified to a pinhole view of a chosen
+ * field of view and maps its errors back onto the fisheye image).
+ *
+ * vfs_rectify_rotations (host only, no device work): for a rig with
+ * X1 = R X0 + t (R row-major 9 doubles, t 3 doubles), rotations Rv0, Rv1
+ * (row-major, caller's 9 doubles each) of a shared virtual orientation:
+ * X_v = Rv0 X0 = Rv1 X1 - (b, 0, 0) with b = |t| returned in *baseline
+ * (may be NULL).  Virtual x runs along R^T t, virtual y is perpendicular to
+ * it and to the mean of the two optical axes, z = x cross y.  The virtual
+ * pair is the pinhole rig R = I, t = (b, 0, 0), whose trajectory field is
+ * (1, 0) everywhere.  VFS_E_INVALID for t = 0, VFS_E_MODEL if t lies along
+ * the mean optical axis. */
+vfs_status vfs_rectify_rotations(const double R[9], const double t[3], double Rv0[9], double Rv1[9],
+                                 double* baseline);
+
+/* Virtual pinhole view of a camera image: for each pixel p of `pinhole`
+ * (host, model VFS_PINHOLE; its width x height is the output size), the ray
+ * Rv^T ((p - c) / f, 1) is projected into `cam` (host, any model); inside
+ * cam's circular mask (fov_deg) dst = bilinear sample of src there (taps
+ * clamped) and valid = 1, elsewhere dst = 0 and valid = 0.  src: device,
+ * cam->height rows of src_pitch floats; dst and valid (device, valid may be
+ * NULL): pinhole->height rows of dst_pitch elements.  Geometry in FP64,
+ * samples in FP32.  Asynchronous on hip_stream. */
+vfs_status vfs_rectify(const vfs_camera* cam, const double Rv[9], const vfs_camera* pinhole, const float* src,
+                       size_t src_pitch, float* dst, size_t dst_pitch, uint8_t* valid, void* hip_stream);
+
+/* The way back: for each pixel q of `cam` inside its circular mask, the ray
+ * pi^-1(q) rotated by Rv; if it lands at a point p inside the pinhole view
+ * (in front of it, within [0, W-1] x [0, H-1]) and the four bilinear taps
+ * around p are valid (field_valid, device, may be NULL = all valid), dst =
+ * bilinear sample of field at p and valid = 1; else dst = 0, valid = 0.
+ * field / field_valid: pinhole->height rows of field_pitch elements; dst /
+ * valid (valid may be NULL): cam->height rows of dst_pitch elements. */
+vfs_status vfs_unrectify(const vfs_camera* cam, const double Rv[9], const vfs_camera* pinhole, const float* field,
+                         const uint8_t* field_valid, size_t field_pitch, float* dst, size_t dst_pitch,
+                         uint8_t* valid, void* hip_stream);
+
 /* ---- Measurement: when enabled, vfs_solve_batch records HIP events on its
  * stream around the level-0 primal-dual launches that each carry several
  * iterations of Eq. (11) in one pass over memory (the dominant kernel) and

@@ -41,6 +41,12 @@ oracle itself; the tests named live in ``tests/``):
 * ``linearise`` -- the warped tangent is unit length and radial away from
   the epipole of a radial field, goes to zero approaching it and is
   Lipschitz across it (test_oracle_solver).
+* ``rectify_rotations`` / ``rectify`` / ``unrectify`` -- the two virtual
+  cameras differ by a pure x-translation for random rigs; rectified renders
+  match the renderer's own pinhole renders of the same scene from both
+  camera centres, and plausible wrong rotations do not; the round trip
+  returns a smooth image; a pinhole camera is its own view
+  (test_oracle_rectify).
 * ``rank_transform`` -- equals its definition written out in plain loops,
   ties included; invariant under strictly increasing intensity maps and
   transposition (test_oracle_rank).
@@ -211,6 +217,42 @@ def prerotate(I1, cf):
     out = np.zeros_like(I1)
     lib().or_prerotate(_p(I1), W, H, _p(cf), _p(out))
     return out
+
+
+def rectify_rotations(R, t):
+    """(Rv0, Rv1, baseline): shared virtual orientation of a rig (see the C file)."""
+    R = np.ascontiguousarray(R, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    a, b = np.zeros(9), np.zeros(9)
+    base = ctypes.c_double()
+    st = lib().or_rectify_rotations(_p(R), _p(t), _p(a), _p(b), ctypes.byref(base))
+    if st != 0:
+        raise ValueError(f"rectify_rotations: status {st}")
+    return a.reshape(3, 3), b.reshape(3, 3), base.value
+
+
+def rectify(cam: dict, Rv, pinhole: dict, src):
+    """(image, valid) of the pinhole view of a camera image."""
+    src = _d(src)
+    Rv = np.ascontiguousarray(Rv, np.float64)
+    out = np.zeros((pinhole["height"], pinhole["width"]))
+    valid = np.zeros(out.shape, np.uint8)
+    c, pn = _cam(cam), _cam(pinhole)
+    lib().or_rectify(ctypes.byref(c), _p(Rv), ctypes.byref(pn), _p(src), _p(out), _p(valid))
+    return out, valid
+
+
+def unrectify(cam: dict, Rv, pinhole: dict, field, field_valid=None):
+    """(values, valid) of a pinhole-view field at the camera's pixels."""
+    field = _d(field)
+    Rv = np.ascontiguousarray(Rv, np.float64)
+    out = np.zeros((cam["height"], cam["width"]))
+    valid = np.zeros(out.shape, np.uint8)
+    fv = None if field_valid is None else _u8(field_valid)
+    c, pn = _cam(cam), _cam(pinhole)
+    lib().or_unrectify(ctypes.byref(c), _p(Rv), ctypes.byref(pn), _p(field), None if fv is None else _p(fv),
+                       _p(out), _p(valid))
+    return out, valid
 
 
 def trajectory_field(cam0: dict, R, t, level: int):

@@ -356,6 +356,129 @@ void or_rank_transform(const double *I, int W, int H, int r, double *out)
         }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Rectification to a virtual pinhole view and back (Sec. V-A compares the   */
+/* method with the same energy run on images rectified to a pinhole view of */
+/* a chosen field of view, and shows its errors on the fisheye image).      */
+/* The virtual orientation: x along the baseline t' = R^T t (camera 0's      */
+/* frame), y perpendicular to x and to the mean of the two optical axes,    */
+/* z = x cross y; Rv0 maps camera-0 vectors, Rv1 = Rv0 R^T camera-1 vectors. */
+/* Then X_v1 = X_v0 + (|t|, 0, 0): a pinhole pair translated along x.       */
+/* ------------------------------------------------------------------------ */
+
+/* Positions within this distance (pixels) outside the image still count as */
+/* inside: they arise from rounding at the border (taps are clamped).        */
+#define OR_EDGE 1e-6
+
+static void or_cross(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void or_unit(double a[3])
+{
+    double n = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    a[0] /= n; a[1] /= n; a[2] /= n;
+}
+
+int or_rectify_rotations(const double R[9], const double t[3], double Rv0[9], double Rv1[9], double *baseline)
+{
+    double x[3], axis[3], y[3], z[3];
+    for (int k = 0; k < 3; ++k) {
+        x[k] = 0.0;
+        for (int a = 0; a < 3; ++a) x[k] += R[3 * a + k] * t[a];       /* (R^T t)_k */
+        axis[k] = 0.5 * ((k == 2) + R[3 * 2 + k]);                    /* camera 1's axis is R^T e_z */
+    }
+    *baseline = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    if (!(*baseline > 0.0)) return OR_E_INVALID;
+    or_unit(x);
+    or_cross(axis, x, y);
+    if (!(sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]) > 1e-9)) return OR_E_MODEL;
+    or_unit(y);
+    or_cross(x, y, z);
+    for (int k = 0; k < 3; ++k) {
+        Rv0[k] = x[k];
+        Rv0[3 + k] = y[k];
+        Rv0[6 + k] = z[k];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += Rv0[3 * i + k] * R[3 * j + k];
+            Rv1[3 * i + j] = acc;
+        }
+    return OR_OK;
+}
+
+/* Pinhole view of a camera image: pixel p of the view sees the ray         */
+/* Rv^T ((p - c)/f, 1); it takes the bilinear sample of the image where the */
+/* camera sees that ray, if the camera's circular mask holds it (else 0,   */
+/* valid 0).  Images row-major, pitch = width.                              */
+void or_rectify(const or_camera *cam, const double Rv[9], const or_camera *pin, const double *src, double *dst,
+                unsigned char *valid)
+{
+    double half = 0.5 * cam->fov_deg * OR_PI / 180.0;
+    double rmax = or_theta_d(cam, half);
+    int Wp = pin->width, Hp = pin->height;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < Hp; ++i)
+        for (int j = 0; j < Wp; ++j) {
+            double v[3] = {(j - pin->cx) / pin->fx, (i - pin->cy) / pin->fy, 1.0}, X[3], x[2];
+            for (int a = 0; a < 3; ++a) X[a] = Rv[a] * v[0] + Rv[3 + a] * v[1] + Rv[6 + a] * v[2];
+            size_t o = (size_t)i * Wp + j;
+            dst[o] = 0.0;
+            valid[o] = 0;
+            if (!or_project(cam, X, x)) continue;
+            double theta = atan2(sqrt(X[0] * X[0] + X[1] * X[1]), X[2]);
+            double mx = (x[0] - cam->cx) / cam->fx, my = (x[1] - cam->cy) / cam->fy;
+            if (theta > half || sqrt(mx * mx + my * my) > rmax) continue;
+            if (x[0] < -OR_EDGE || x[0] > cam->width - 1.0 + OR_EDGE || x[1] < -OR_EDGE ||
+                x[1] > cam->height - 1.0 + OR_EDGE)
+                continue;
+            dst[o] = or_bilinear(src, cam->width, cam->height, x[0], x[1]);
+            valid[o] = 1;
+        }
+}
+
+/* The way back: camera pixel q inside its mask sees pi^-1(q); rotated by   */
+/* Rv it lands in the pinhole view at p; if p is inside the view and the    */
+/* four bilinear taps around p are valid, the field's bilinear sample there */
+/* (else 0, valid 0).                                                       */
+void or_unrectify(const or_camera *cam, const double Rv[9], const or_camera *pin, const double *field,
+                  const unsigned char *field_valid, double *dst, unsigned char *valid)
+{
+    double half = 0.5 * cam->fov_deg * OR_PI / 180.0;
+    double rmax = or_theta_d(cam, half), th_lim = or_theta_limit(cam);
+    int W = cam->width, H = cam->height, Wp = pin->width, Hp = pin->height;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            size_t o = (size_t)i * W + j;
+            dst[o] = 0.0;
+            valid[o] = 0;
+            double mx = (j - cam->cx) / cam->fx, my = (i - cam->cy) / cam->fy;
+            if (sqrt(mx * mx + my * my) > rmax) continue;
+            double r[3], V[3];
+            or_unproject(cam, th_lim, j, i, r);
+            for (int a = 0; a < 3; ++a) V[a] = Rv[3 * a] * r[0] + Rv[3 * a + 1] * r[1] + Rv[3 * a + 2] * r[2];
+            if (!(V[2] > 0.0)) continue;
+            double px = pin->cx + pin->fx * V[0] / V[2], py = pin->cy + pin->fy * V[1] / V[2];
+            if (px < -OR_EDGE || px > Wp - 1.0 + OR_EDGE || py < -OR_EDGE || py > Hp - 1.0 + OR_EDGE) continue;
+            int x0 = (int)floor(px), y0 = (int)floor(py), x1 = x0 + 1, y1 = y0 + 1;
+            x0 = x0 < 0 ? 0 : (x0 > Wp - 1 ? Wp - 1 : x0);
+            y0 = y0 < 0 ? 0 : (y0 > Hp - 1 ? Hp - 1 : y0);
+            x1 = x1 < 0 ? 0 : (x1 > Wp - 1 ? Wp - 1 : x1);
+            y1 = y1 < 0 ? 0 : (y1 > Hp - 1 ? Hp - 1 : y1);
+            if (field_valid && !(field_valid[(size_t)y0 * Wp + x0] && field_valid[(size_t)y0 * Wp + x1] &&
+                                 field_valid[(size_t)y1 * Wp + x0] && field_valid[(size_t)y1 * Wp + x1]))
+                continue;
+            dst[o] = or_bilinear(field, Wp, Hp, px, py);
+            valid[o] = 1;
+        }
+}
+
 void or_prerotate(const double *I1, int W, int H, const double *cf, double *out)
 {
 #pragma omp parallel for schedule(static)

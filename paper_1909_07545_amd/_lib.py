@@ -86,6 +86,9 @@ def lib():
         L.vfs_profile_read.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int]
         L.vfs_params_default.argtypes = [_vp]
         L.vfs_step_rank.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
+        L.vfs_rectify_rotations.argtypes = [_vp] * 5
+        L.vfs_rectify.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _vp]
+        L.vfs_unrectify.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _vp]
         L.vfs_step_energy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t] + [_vp] * 7 + [_vp]
         L.vfs_step_pd_energy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t] + [_vp] * 11 + \
             [_vp, ctypes.c_int, _vp, _vp]
@@ -293,6 +296,33 @@ def step_upsample(flags_c, u_c, w_c, u_f, w_f, stream=None):
 def step_triangulate(rig: Rig, w, depth, z=None, valid=None, stream=None):
     _check(lib().vfs_step_triangulate(rig.handle, rig.width, _ptr(w), _ptr(depth), _ptr(z), _ptr(valid),
                                       _stream(stream)))
+
+
+def rectify_rotations(R, t):
+    """(Rv0, Rv1, baseline) of the shared virtual orientation of a rig
+    (vfs_rectify_rotations; host only)."""
+    Rr = (ctypes.c_double * 9)(*np.asarray(R, np.float64).reshape(9).tolist())
+    tt = (ctypes.c_double * 3)(*np.asarray(t, np.float64).reshape(3).tolist())
+    a, b, base = (ctypes.c_double * 9)(), (ctypes.c_double * 9)(), ctypes.c_double()
+    _check(lib().vfs_rectify_rotations(Rr, tt, a, b, ctypes.byref(base)))
+    return np.array(a[:]).reshape(3, 3), np.array(b[:]).reshape(3, 3), base.value
+
+
+def rectify(cam: dict, Rv, pinhole: dict, src, dst, valid=None, stream=None):
+    """Virtual pinhole view of a camera image (vfs_rectify): src (H, W) of
+    cam, dst / valid (Hp, Wp) of the pinhole view."""
+    c, pn = _camera(cam), _camera(pinhole)
+    R9 = (ctypes.c_double * 9)(*np.asarray(Rv, np.float64).reshape(9).tolist())
+    _check(lib().vfs_rectify(ctypes.byref(c), R9, ctypes.byref(pn), _ptr(src), src.shape[1], _ptr(dst),
+                             dst.shape[1], _ptr(valid), _stream(stream)))
+
+
+def unrectify(cam: dict, Rv, pinhole: dict, field, dst, field_valid=None, valid=None, stream=None):
+    """A pinhole-view field sampled at the camera's pixels (vfs_unrectify)."""
+    c, pn = _camera(cam), _camera(pinhole)
+    R9 = (ctypes.c_double * 9)(*np.asarray(Rv, np.float64).reshape(9).tolist())
+    _check(lib().vfs_unrectify(ctypes.byref(c), R9, ctypes.byref(pn), _ptr(field), _ptr(field_valid),
+                               field.shape[1], _ptr(dst), dst.shape[1], _ptr(valid), _stream(stream)))
 
 
 def profile_enable(rig: Rig, on: bool = True):

@@ -1000,9 +1000,9 @@ vfs_status vfs_profile_enable(vfs_rig* r, int enable)
 
 vfs_status vfs_profile_read(vfs_rig* r, double* ms, long long* launches, int* iters_per_launch, int reset)
 {
-    if (iters_per_launch) *iters_per_launch = r->pass_iters;
     g_err[0] = 0;
     if (!r) return fail(VFS_E_INVALID, "rig is NULL");
+    if (iters_per_launch) *iters_per_launch = r->pass_iters;
     if (!r->events.empty()) {
         HIP_OK(hipStreamSynchronize(r->last_stream));
         for (auto& e : r->events) {
@@ -1020,6 +1020,84 @@ vfs_status vfs_profile_read(vfs_rig* r, double* ms, long long* launches, int* it
         r->ms = 0.0;
         r->launches = 0;
     }
+    return VFS_OK;
+}
+
+vfs_status vfs_rectify_rotations(const double R[9], const double t[3], double Rv0[9], double Rv1[9], double* baseline)
+{
+    g_err[0] = 0;
+    if (!R || !t || !Rv0 || !Rv1) return fail(VFS_E_INVALID, "bad argument");
+    // baseline direction t' = R^T t in camera 0's frame, and the mean of the two optical axes
+    double ex[3], a[3];
+    for (int k = 0; k < 3; ++k) {
+        ex[k] = R[k] * t[0] + R[3 + k] * t[1] + R[6 + k] * t[2];
+        a[k] = (k == 2 ? 1.0 : 0.0) + R[6 + k];
+    }
+    const double b = sqrt(ex[0] * ex[0] + ex[1] * ex[1] + ex[2] * ex[2]);
+    if (!(b > 0.0)) return fail(VFS_E_INVALID, "zero translation");
+    for (double& v : ex) v /= b;
+    double ey[3] = {a[1] * ex[2] - a[2] * ex[1], a[2] * ex[0] - a[0] * ex[2], a[0] * ex[1] - a[1] * ex[0]};
+    const double ny = sqrt(ey[0] * ey[0] + ey[1] * ey[1] + ey[2] * ey[2]);
+    if (!(ny > 1e-9)) return fail(VFS_E_MODEL, "baseline along the viewing direction: no side-by-side view");
+    for (double& v : ey) v /= ny;
+    const double ez[3] = {ex[1] * ey[2] - ex[2] * ey[1], ex[2] * ey[0] - ex[0] * ey[2], ex[0] * ey[1] - ex[1] * ey[0]};
+    for (int k = 0; k < 3; ++k) {
+        Rv0[k] = ex[k];
+        Rv0[3 + k] = ey[k];
+        Rv0[6 + k] = ez[k];
+    }
+    // Rv1 = Rv0 R^T: camera 1's frame to the shared virtual orientation
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            Rv1[3 * r + c] = Rv0[3 * r] * R[3 * c] + Rv0[3 * r + 1] * R[3 * c + 1] + Rv0[3 * r + 2] * R[3 * c + 2];
+    if (baseline) *baseline = b;
+    return VFS_OK;
+}
+
+namespace {
+
+vfs_status rectify_geom(const vfs_camera* cam, const double Rv[9], const vfs_camera* pin, vfs::RectifyGeom& g)
+{
+    if (vfs_status st = check_camera(cam, "cam")) return st;
+    if (vfs_status st = check_camera(pin, "pinhole")) return st;
+    if (pin->model != VFS_PINHOLE) return fail(VFS_E_INVALID, "the virtual view must be a pinhole camera");
+    if (!Rv) return fail(VFS_E_INVALID, "Rv is NULL");
+    g.cam = to_cam(*cam);
+    g.pin = to_cam(*pin);
+    for (int k = 0; k < 9; ++k) g.Rv[k] = Rv[k];
+    g.half = 0.5 * cam->fov_deg * kPi / 180.0;
+    g.rmax = vfs::cam_rd(g.cam, g.half);
+    return VFS_OK;
+}
+
+}  // namespace
+
+vfs_status vfs_rectify(const vfs_camera* cam, const double Rv[9], const vfs_camera* pinhole, const float* src,
+                       size_t src_pitch, float* dst, size_t dst_pitch, uint8_t* valid, void* hip_stream)
+{
+    g_err[0] = 0;
+    vfs::RectifyGeom g{};
+    if (vfs_status st = rectify_geom(cam, Rv, pinhole, g)) return st;
+    if (!src || !dst || src_pitch < size_t(cam->width) || dst_pitch < size_t(pinhole->width))
+        return fail(VFS_E_INVALID, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    vfs::launch_rectify(g, src, src_pitch, dst, dst_pitch, valid, s);
+    HIP_OK(hipGetLastError());
+    return VFS_OK;
+}
+
+vfs_status vfs_unrectify(const vfs_camera* cam, const double Rv[9], const vfs_camera* pinhole, const float* field,
+                         const uint8_t* field_valid, size_t field_pitch, float* dst, size_t dst_pitch, uint8_t* valid,
+                         void* hip_stream)
+{
+    g_err[0] = 0;
+    vfs::RectifyGeom g{};
+    if (vfs_status st = rectify_geom(cam, Rv, pinhole, g)) return st;
+    if (!field || !dst || field_pitch < size_t(pinhole->width) || dst_pitch < size_t(cam->width))
+        return fail(VFS_E_INVALID, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    vfs::launch_unrectify(g, field, field_valid, field_pitch, dst, dst_pitch, valid, s);
+    HIP_OK(hipGetLastError());
     return VFS_OK;
 }
 

@@ -170,6 +170,15 @@ struct RigGeom {
     double eps;         // step along t' of the trajectory-field construction
 };
 
+// A camera and a virtual pinhole view rotated against it (X_v = Rv X_cam).
+struct RectifyGeom {
+    Cam cam;            // the real camera (any model)
+    Cam pin;            // the virtual view (pinhole model)
+    double Rv[9];       // row-major
+    double rmax;        // radial limit of the camera's mask, r_d(FOV / 2)
+    double half;        // FOV / 2 (radians)
+};
+
 // ----------------------------------------------------------------- compact storage
 // The dual variables (p, q) and the tensor pack (t11, t12, t22, I_u) are
 // stored as 32-bit floats (ST_F32), IEEE half (ST_F16) or bfloat16
@@ -364,6 +373,10 @@ void launch_rank(const Launch& lc, hipStream_t s);
 void launch_upsample(const Launch& lc, int tgv, int storage, hipStream_t s);  // level + 1 -> level
 void launch_zero_state(const Launch& lc, int tgv, int storage, hipStream_t s);
 void launch_triangulate(const Launch& lc, hipStream_t s);                    // level 0
+void launch_rectify(const RectifyGeom& g, const float* src, size_t src_pitch, float* dst, size_t dst_pitch,
+                    uint8_t* valid, hipStream_t s);
+void launch_unrectify(const RectifyGeom& g, const float* field, const uint8_t* field_valid, size_t field_pitch,
+                      float* dst, size_t dst_pitch, uint8_t* valid, hipStream_t s);
 
 // Primal-dual iteration (Eq. (11)).
 enum PdMode { PD_DUAL_FIRST = 0, PD_FUSED = 1, PD_PRIMAL_LAST = 2, PD_FUSED2 = 3, PD_FUSED3 = 4, PD_FUSED4 = 5 };

@@ -79,6 +79,11 @@ CONFIGS = {
     "r200": _cfg("r200", seed_offset=11, name="ragged200", width=200, height=136, model="kb",
                  f=None, fov_deg=185.0, kb_range=0.05, baseline=0.08, rot_deg=3.0, scene="room",
                  depth_range=(1.0, 10.0), tex_k=(0.5, 8.0), levels=3, warps=4, iters=30),
+    # comparison with rectified pinhole views (the paper's comparison: 800x800,
+    # 180-degree fisheye, the same schedule for both)
+    "rect800": _cfg("rect800", seed_offset=14, name="rect800", width=800, height=800, model="equidistant",
+                    f=None, fov_deg=180.0, kb_range=0.0, baseline=0.12, rot_deg=2.0, scene="room",
+                    depth_range=(1.0, 10.0), tex_k=(0.5, 8.0), levels=5, warps=10, iters=100, supersample=2),
 }
 
 # Serving mix: 512 requests, sizes 320x240 / 640x480 / 1024x768 in the ratio

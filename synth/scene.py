@@ -333,17 +333,37 @@ def _render(cam, scene, origin, Rcw, ss, rows=128):
     return img.numpy()
 
 
+def make_scene(rig, cfg, pair=0):
+    """The scene of pair ``pair`` of a configuration (in camera 0's frame)."""
+    ss_scene = np.random.SeedSequence(cfg["seed"]).spawn(4)[1]
+    s_rng = np.random.default_rng(ss_scene.spawn(pair + 1)[pair])
+    R, t = np.asarray(rig["R"]), np.asarray(rig["t"])
+    if cfg["scene"] == "plane":
+        return Plane(s_rng, cfg)
+    return Room(s_rng, cfg, [np.zeros(3), -R.T @ t])
+
+
+def pinhole_view(size, fov_deg):
+    """Square pinhole camera whose horizontal field of view is ``fov_deg``;
+    its circular mask (``fov_deg`` of the dict) reaches the image corners."""
+    half = np.deg2rad(fov_deg) / 2
+    f = (size / 2.0) / np.tan(half)
+    diag = 2.0 * np.rad2deg(np.arctan(np.sqrt(2.0) * np.tan(half) * (1.0 + 1.0 / size)))
+    return make_camera("pinhole", size, size, f, min(diag, 179.9))
+
+
+def render_view(cam, scene, origin, Rcw, ss):
+    """Image of any camera at ``origin`` whose rays in camera 0's frame are Rcw @ r."""
+    return _render(cam, scene, origin, Rcw, ss).astype(np.float32)
+
+
 def render_pair(rig, cfg, pair=0, with_gt=True):
     """(I0, I1, gt) for pair ``pair`` of a configuration's batch."""
-    ss_rig, ss_scene, ss_tex, ss_noise = np.random.SeedSequence(cfg["seed"]).spawn(4)
-    s_rng = np.random.default_rng(ss_scene.spawn(pair + 1)[pair])
+    ss_noise = np.random.SeedSequence(cfg["seed"]).spawn(4)[3]
     n_rng = np.random.default_rng(ss_noise.spawn(pair + 1)[pair])
     R, t = np.asarray(rig["R"]), np.asarray(rig["t"])
     c1_centre = -R.T @ t
-    if cfg["scene"] == "plane":
-        scene = Plane(s_rng, cfg)
-    else:
-        scene = Room(s_rng, cfg, [np.zeros(3), c1_centre])
+    scene = make_scene(rig, cfg, pair)
     ss = int(cfg.get("supersample", 1))
     I0 = _render(rig["cam0"], scene, np.zeros(3), np.eye(3), ss)
     I1 = _render(rig["cam1"], scene, c1_centre, R.T, ss)
