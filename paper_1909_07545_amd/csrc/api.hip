@@ -489,6 +489,7 @@ vfs_status vfs_rig_create(const vfs_camera* cam0, const vfs_camera* cam1, const 
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     auto cleanup = [&](vfs_status e) { delete r; return e; };
     if (hipGetDevice(&r->device) != hipSuccess) return cleanup(fail(VFS_E_DEVICE, "hipGetDevice failed"));
+    prepare_pd();
     if (hipMalloc(&r->geom_dev, sizeof(RigGeom)) != hipSuccess) return cleanup(fail(VFS_E_NOMEM, "rig geometry"));
     if (hipMemcpyAsync(r->geom_dev, &g, sizeof(RigGeom), hipMemcpyHostToDevice, s) != hipSuccess)
         return cleanup(fail(VFS_E_DEVICE, "copying rig geometry"));

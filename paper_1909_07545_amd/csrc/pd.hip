@@ -25,24 +25,26 @@
 //
 // Work decomposition: one 64-lane wavefront owns a strip of columns (62 for
 // the one-iteration modes: lanes 1..62, lanes 0 and 63 are the x-halo; 60 for
-// PD_FUSED2: lanes 2..61) and marches down 16 rows plus a halo above and
-// below, keeping the rows it still needs in registers and exchanging
-// x-neighbours by lane shifts.  A workgroup holds 4 wavefronts stacked
-// vertically.  Workgroups are renumbered so that the blocks the dispatcher
-// places on one XCD cover a contiguous band of tiles (their halo re-reads
-// then hit that XCD's L2).
+// PD_FUSED2: lanes 2..61; 64 - 2N for N iterations) and marches down a
+// segment of rows plus a halo above and below, keeping the rows it still
+// needs in registers and exchanging x-neighbours by lane shifts.  The four
+// wavefronts of a workgroup take four neighbouring strips of the same
+// segment, and workgroups are renumbered so that the blocks the dispatcher
+// places on one XCD cover a contiguous band of tasks: strips that share
+// halo columns are read at the same time through the same L2.  The segment
+// height is a run-time argument chosen by the host per launch (march_shape),
+// so every grid runs the same code and a pair's result does not depend on
+// the batch it is launched with.
 #include "vfs_internal.h"
+
+#include <map>
+#include <mutex>
+#include <utility>
 
 namespace vfs {
 
 namespace {
 
-#ifndef VFS_PD_BY
-#define VFS_PD_BY 16
-#endif
-#ifndef VFS_PD2_BY
-#define VFS_PD2_BY 16
-#endif
 #ifndef VFS_PD_DPP
 #define VFS_PD_DPP 1
 #endif
@@ -50,14 +52,17 @@ namespace {
 constexpr int kLanes = 64;
 constexpr int kWaves = 4;            // wavefronts per workgroup
 constexpr int kCols = kLanes - 2;    // owned columns per wavefront, one-iteration modes
-constexpr int kBY = VFS_PD_BY;       // owned rows per wavefront, one-iteration modes (large grids)
 constexpr int kCols2 = kLanes - 4;   // owned columns per wavefront, PD_FUSED2
-constexpr int kBY2 = VFS_PD2_BY;     // owned rows per wavefront, PD_FUSED2 (large grids)
-// Small grids (few workgroups: coarse levels, small images) cannot hide the
-// memory latency of each row step of the march behind other wavefronts; they
-// march kBYs rows instead, for 4x the wavefronts and a shorter march.
+// Segment heights (rows per wavefront march).  With enough work for several
+// rounds of resident wavefronts: marches of about kBY rows, their count
+// rounded to whole rounds (short marches keep the rows in flight at any
+// moment close together, measured faster than long ones at equal traffic).
+// With less: one round of marches as long as fit, but at least kBYs rows
+// (long marches re-read fewer halo rows, and no partly filled last round
+// idles the chip).
+constexpr int kBY = 16;
 constexpr int kBYs = 4;
-constexpr long long kSmallGrid = 2048;   // workgroups at the large-grid height below which kBYs is used
+constexpr long long kRoundsForShort = 4;
 constexpr int kXcds = 8;
 
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -276,31 +281,45 @@ __device__ inline int logical_block()
     return xcd < rn ? xcd * (qn + 1) + k : rn * (qn + 1) + (xcd - rn) * qn + k;
 }
 
+// The march of this wavefront: strip tx of `cols` columns and rows from y0 of
+// pair `pair`; false if the grid's last workgroup has no task for it.
+struct Task {
+    int tx, y0, pair;
+};
+
+__device__ inline bool task_of(const PdArgs& a, int cols, int by, int segs, Task& t)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    const long long task = (long long)logical_block() * kWaves + wave;
+    const int tiles_x = (a.lc.g.W[a.lc.gl] + cols - 1) / cols;
+    const long long pair = task / ((long long)tiles_x * segs);
+    t.tx = int(task % tiles_x);
+    t.y0 = int((task / tiles_x) % segs) * by;
+    t.pair = int(pair);
+    return pair < a.lc.n;
+}
+
 // One iteration (PD_FUSED) or its first / last half (PD_DUAL_FIRST, PD_PRIMAL_LAST).
-template <int MODE, bool TGV, int S, int BY>
-__global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
+template <int MODE, bool TGV, int S>
+__global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a, int by, int segs)
 {
     constexpr bool PRIMAL = MODE != PD_DUAL_FIRST;
     constexpr bool DUAL = MODE != PD_PRIMAL_LAST;
 
-    const int logical = logical_block();
-    const int tiles_x = (a.lc.g.W[a.lc.gl] + kCols - 1) / kCols;
-    const int tiles_y = (a.lc.g.H[a.lc.gl] + BY * kWaves - 1) / (BY * kWaves);
-    const int tx = logical % tiles_x;
-    const int ty = (logical / tiles_x) % tiles_y;
-    const int pair = logical / (tiles_x * tiles_y);
+    Task tk;
+    if (!task_of(a, kCols, by, segs, tk)) return;
     Planes P;
-    if (!planes_of<S>(a, pair, P)) return;
+    if (!planes_of<S>(a, tk.pair, P)) return;
+    const int tx = tk.tx;
     if (tx * kCols >= P.W) return;
 
     const int lane = threadIdx.x & (kLanes - 1);
-    const int wave = threadIdx.x / kLanes;
     const int x = tx * kCols - 1 + lane;
     const bool in_x = x >= 0 && x < P.W;
     const bool owner = lane >= 1 && lane <= kCols && in_x;
-    const int y0 = (ty * kWaves + wave) * BY;
+    const int y0 = tk.y0;
     if (y0 >= P.H) return;
-    const int y1 = min(y0 + BY, P.H);           // owned rows [y0, y1)
+    const int y1 = min(y0 + by, P.H);           // owned rows [y0, y1)
     const float a0 = a.alpha0, a1 = a.alpha1;
 
     // row r - 1 as the dual step needs it
@@ -377,27 +396,23 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a)
 // read for A's first "above").  Column validity shrinks by one lane per
 // stage away from the wavefront's edges: A is exact on lanes 1..63, B on
 // 1..62, C on 2..62, D on 2..61 -- the owned lanes.
-template <bool TGV, int S, int BY>
-__global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a)
+template <bool TGV, int S>
+__global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, int segs)
 {
-    const int logical = logical_block();
-    const int tiles_x = (a.lc.g.W[a.lc.gl] + kCols2 - 1) / kCols2;
-    const int tiles_y = (a.lc.g.H[a.lc.gl] + BY * kWaves - 1) / (BY * kWaves);
-    const int tx = logical % tiles_x;
-    const int ty = (logical / tiles_x) % tiles_y;
-    const int pair = logical / (tiles_x * tiles_y);
+    Task tk;
+    if (!task_of(a, kCols2, by, segs, tk)) return;
     Planes P;
-    if (!planes_of<S>(a, pair, P)) return;
+    if (!planes_of<S>(a, tk.pair, P)) return;
+    const int tx = tk.tx;
     if (tx * kCols2 >= P.W) return;
 
     const int lane = threadIdx.x & (kLanes - 1);
-    const int wave = threadIdx.x / kLanes;
     const int x = tx * kCols2 - 2 + lane;
     const bool in_x = x >= 0 && x < P.W;
     const bool owner = lane >= 2 && lane <= kCols2 + 1 && in_x;
-    const int y0 = (ty * kWaves + wave) * BY;
+    const int y0 = tk.y0;
     if (y0 >= P.H) return;
-    const int y1 = min(y0 + BY, P.H);
+    const int y1 = min(y0 + by, P.H);
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
 
     // iteration 1: "above" of row r-1, and row r-1 as B needs it
@@ -546,29 +561,26 @@ template <> struct TensorRaw<ST_F32> {
     __device__ static float4 identity() { return make_float4(1.f, 0.f, 1.f, 0.f); }
 };
 
-template <bool TGV, int S, int BY, int N>
-__global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) void pdn_kernel(PdArgs a)
+template <bool TGV, int S, int N>
+__global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) void pdn_kernel(PdArgs a, int by,
+                                                                                               int segs)
 {
     constexpr int kColsN = kLanes - 2 * N;
     constexpr int D = 2 * N;    // depth of the constants' delay line
-    const int logical = logical_block();
-    const int tiles_x = (a.lc.g.W[a.lc.gl] + kColsN - 1) / kColsN;
-    const int tiles_y = (a.lc.g.H[a.lc.gl] + BY * kWaves - 1) / (BY * kWaves);
-    const int tx = logical % tiles_x;
-    const int ty = (logical / tiles_x) % tiles_y;
-    const int pair = logical / (tiles_x * tiles_y);
+    Task tk;
+    if (!task_of(a, kColsN, by, segs, tk)) return;
     Planes P;
-    if (!planes_of<S>(a, pair, P)) return;
+    if (!planes_of<S>(a, tk.pair, P)) return;
+    const int tx = tk.tx;
     if (tx * kColsN >= P.W) return;
 
     const int lane = threadIdx.x & (kLanes - 1);
-    const int wave = threadIdx.x / kLanes;
     const int x = tx * kColsN - N + lane;
     const bool in_x = x >= 0 && x < P.W;
     const bool owner = lane >= N && lane < N + kColsN && in_x;
-    const int y0 = (ty * kWaves + wave) * BY;
+    const int y0 = tk.y0;
     if (y0 >= P.H) return;
-    const int y1 = min(y0 + BY, P.H);
+    const int y1 = min(y0 + by, P.H);
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
 
     // constants of rows r - d (d = 0 .. D-1) after the shift of step r: the
@@ -614,9 +626,7 @@ __global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) v
     const int r_lo = y0 - (N - 1), r_hi = y1 + 2 * N - 2, r_load = y1 + N - 1;
     // no prefetch here: its registers would cost a wavefront per SIMD, which
     // is worth more on the bandwidth-bound grids this kernel serves
-    // (measured).  The choice must not depend on BY: the two march heights
-    // must compile to the same per-pixel arithmetic, so that a pair's result
-    // does not depend on the grid (batch) it runs in.
+    // (measured)
     constexpr bool PF = false;
     Row nxt = zero_row();
     if constexpr (PF) nxt = load_row<TGV, true, S>(P, x, r_lo, in_x);
@@ -711,45 +721,82 @@ __global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) v
     }
 }
 
-// Workgroups of a launch whose wavefronts own `cols` columns and `by` rows.
-inline long long grid_blocks(const PdArgs& a, int cols, int by)
+// Wavefronts of a kernel that the current device holds at once (its
+// occupancy times the compute units), cached per kernel and device.
+template <typename K>
+long long resident_waves(K kernel)
 {
-    const long long tiles_x = (a.lc.g.W[a.lc.gl] + cols - 1) / cols;
-    const long long tiles_y = (a.lc.g.H[a.lc.gl] + by * kWaves - 1) / (by * kWaves);
-    return tiles_x * tiles_y * a.lc.n;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, long long> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), dev);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int blocks = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, kLanes * kWaves, 0) != hipSuccess || blocks < 1)
+        blocks = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    const long long w = (long long)blocks * cus * kWaves;
+    cache.emplace(key, w);
+    return w;
+}
+
+// Segment height, segment count and workgroups of a launch whose wavefronts
+// own `cols` columns (blocks = 0: nothing to do).
+struct March {
+    int by, segs;
+    long long blocks;
+};
+
+template <typename K>
+March march_shape(const PdArgs& a, int cols, K kernel)
+{
+    March m{0, 0, 0};
+    const int H = a.lc.g.H[a.lc.gl];
+    const long long strips = (long long)(a.lc.g.W[a.lc.gl] + cols - 1) / cols * a.lc.n;
+    if (strips < 1 || H < 1) return m;
+    const long long slots = resident_waves(kernel);
+    const long long full = strips * ((H + kBY - 1) / kBY);
+    long long segs;
+    if (full >= kRoundsForShort * slots) {
+        const long long rounds = (full + slots / 2) / slots;
+        segs = rounds * slots / strips;
+    } else {
+        segs = slots / strips;
+    }
+    if (segs < 1) segs = 1;
+    int by = int((H + segs - 1) / segs);
+    if (by < kBYs) by = kBYs;
+    m.by = by;
+    m.segs = (H + by - 1) / by;
+    m.blocks = (strips * m.segs + kWaves - 1) / kWaves;
+    return m;
 }
 
 template <int MODE, bool TGV, int S>
 void launch_mode(const PdArgs& a, hipStream_t s)
 {
-    const long long nb = grid_blocks(a, kCols, kBY);
-    if (nb >= kSmallGrid)
-        hipLaunchKernelGGL((pd_kernel<MODE, TGV, S, kBY>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
-    else
-        hipLaunchKernelGGL((pd_kernel<MODE, TGV, S, kBYs>), dim3(grid_blocks(a, kCols, kBYs)),
-                           dim3(kLanes * kWaves), 0, s, a);
+    const March m = march_shape(a, kCols, pd_kernel<MODE, TGV, S>);
+    if (m.blocks)
+        hipLaunchKernelGGL((pd_kernel<MODE, TGV, S>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
 
 template <bool TGV, int S>
 void launch_fused2(const PdArgs& a, hipStream_t s)
 {
-    const long long nb = grid_blocks(a, kCols2, kBY2);
-    if (nb >= kSmallGrid)
-        hipLaunchKernelGGL((pd2_kernel<TGV, S, kBY2>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
-    else
-        hipLaunchKernelGGL((pd2_kernel<TGV, S, kBYs>), dim3(grid_blocks(a, kCols2, kBYs)),
-                           dim3(kLanes * kWaves), 0, s, a);
+    const March m = march_shape(a, kCols2, pd2_kernel<TGV, S>);
+    if (m.blocks)
+        hipLaunchKernelGGL((pd2_kernel<TGV, S>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
 
 template <bool TGV, int S, int N>
 void launch_fusedn(const PdArgs& a, hipStream_t s)
 {
-    const long long nb = grid_blocks(a, kLanes - 2 * N, kBY2);
-    if (nb >= kSmallGrid)
-        hipLaunchKernelGGL((pdn_kernel<TGV, S, kBY2, N>), dim3(nb), dim3(kLanes * kWaves), 0, s, a);
-    else
-        hipLaunchKernelGGL((pdn_kernel<TGV, S, kBYs, N>), dim3(grid_blocks(a, kLanes - 2 * N, kBYs)),
-                           dim3(kLanes * kWaves), 0, s, a);
+    const March m = march_shape(a, kLanes - 2 * N, pdn_kernel<TGV, S, N>);
+    if (m.blocks)
+        hipLaunchKernelGGL((pdn_kernel<TGV, S, N>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
 
 template <bool TGV, int S>
@@ -763,7 +810,28 @@ void launch_typed(const PdArgs& a, hipStream_t s)
     else launch_mode<PD_PRIMAL_LAST, TGV, S>(a, s);
 }
 
+template <bool TGV, int S>
+void prepare_typed()
+{
+    (void)resident_waves(pd_kernel<PD_DUAL_FIRST, TGV, S>);
+    (void)resident_waves(pd_kernel<PD_FUSED, TGV, S>);
+    (void)resident_waves(pd_kernel<PD_PRIMAL_LAST, TGV, S>);
+    (void)resident_waves(pd2_kernel<TGV, S>);
+    (void)resident_waves(pdn_kernel<TGV, S, 3>);
+    (void)resident_waves(pdn_kernel<TGV, S, 4>);
+}
+
 }  // namespace
+
+void prepare_pd()
+{
+    prepare_typed<true, ST_F32>();
+    prepare_typed<true, ST_F16>();
+    prepare_typed<true, ST_BF16>();
+    prepare_typed<false, ST_F32>();
+    prepare_typed<false, ST_F16>();
+    prepare_typed<false, ST_BF16>();
+}
 
 void launch_pd(const PdArgs& a, hipStream_t s)
 {

@@ -282,6 +282,7 @@ vfs_status make_bucket(vfs_server* sv, const Geometry& g, Bucket*& out)
     CtrlBlock cb{};
     launch_write_ctrl(cb, kMaxBatch, b->ctrl_dev, b->stream);
     if (sv->cfg.use_graphs) {
+        prepare_pd();
         for (int gl = 0; gl < g.L; ++gl)
             for (int full = 0; full < 2; ++full) {
                 if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)

@@ -392,6 +392,9 @@ struct PdArgs {
     int pass;                   // iterations per pass of the multi-iteration launches (2, 3, 4)
 };
 void launch_pd(const PdArgs& a, hipStream_t s);
+// Queries the occupancy the primal-dual launches are sized by, for the
+// current device (once; call before a graph capture of primal-dual work).
+void prepare_pd();
 
 // Linearised energy of Eq. (10) per pair of a launch (fixed-order FP64
 // reduction): partial needs energy_partials(lc) doubles, out lc.n doubles.
