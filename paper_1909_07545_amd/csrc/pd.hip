@@ -43,6 +43,11 @@
 
 namespace vfs {
 
+// Multiply-adds are fused only within one source expression, never across
+// statements, so that code paths which evaluate the same expressions on the
+// same values (the two march directions) give bitwise equal results.
+#pragma clang fp contract(on)
+
 namespace {
 
 #ifndef VFS_PD_DPP
@@ -561,26 +566,13 @@ template <> struct TensorRaw<ST_F32> {
     __device__ static float4 identity() { return make_float4(1.f, 0.f, 1.f, 0.f); }
 };
 
+// Downward march: at step r, iteration i takes its primal step at row r - 2i
+// and its dual step at row r - 2i - 1 (the dual needs xbar of the row below).
 template <bool TGV, int S, int N>
-__global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) void pdn_kernel(PdArgs a, int by,
-                                                                                               int segs)
+__device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int x, bool in_x, bool owner, int y0,
+                                           int y1)
 {
-    constexpr int kColsN = kLanes - 2 * N;
     constexpr int D = 2 * N;    // depth of the constants' delay line
-    Task tk;
-    if (!task_of(a, kColsN, by, segs, tk)) return;
-    Planes P;
-    if (!planes_of<S>(a, tk.pair, P)) return;
-    const int tx = tk.tx;
-    if (tx * kColsN >= P.W) return;
-
-    const int lane = threadIdx.x & (kLanes - 1);
-    const int x = tx * kColsN - N + lane;
-    const bool in_x = x >= 0 && x < P.W;
-    const bool owner = lane >= N && lane < N + kColsN && in_x;
-    const int y0 = tk.y0;
-    if (y0 >= P.H) return;
-    const int y1 = min(y0 + by, P.H);
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
 
     // constants of rows r - d (d = 0 .. D-1) after the shift of step r: the
@@ -719,6 +711,147 @@ __global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) v
         p_m1 = c.p;
         q_m1 = c.q;
     }
+}
+
+// Upward march: at step r (rows decreasing), iteration i takes both its
+// primal and its dual step at row r + i.  The primal step needs the duals of
+// the row above, which iteration i - 1 produced earlier in the same step; the
+// dual step needs xbar of the row below, from iteration i's previous step.
+// Iteration i covers the same rows as in the downward march, so every value
+// is computed from the same inputs.
+template <bool TGV, int S, int N>
+__device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x, bool in_x, bool owner, int y0,
+                                         int y1)
+{
+    const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
+    // constants of rows r + d (d = 0 .. N-1) after the shift of step r
+    using TRaw = typename TensorRaw<S>::type;
+    TRaw tD[N];
+    float rhoD[N];
+    uint64_t fD = 0;
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+        tD[d] = TensorRaw<S>::identity();
+        rhoD[d] = 0.f;
+    }
+    auto flag = [&](int d) { return unsigned(fD >> (8 * d)) & 0xffu; };
+    // per iteration i, from its previous step (row r + 1 + i): primal output,
+    // xbar and dual output
+    float xu[N], xbu[N];
+    float2 xv[N], xbv[N], yp[N];
+    float4 yq[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        xu[i] = 0.f;
+        xbu[i] = 0.f;
+        xv[i] = make_float2(0.f, 0.f);
+        xbv[i] = make_float2(0.f, 0.f);
+        yp[i] = make_float2(0.f, 0.f);
+        yq[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    const int r_hi = y1 + N - 1, r_lo = y0 - (N - 1);
+    Row c = load_row<TGV, true, S>(P, x, r_hi, in_x);
+    for (int r = r_hi; r >= r_lo; --r) {
+        // the row above: iteration 0's y^k there, and the next step's row
+        const Row nx = load_row<TGV, true, S>(P, x, r - 1, in_x);
+#pragma unroll
+        for (int d = N - 1; d > 0; --d) {
+            tD[d] = tD[d - 1];
+            rhoD[d] = rhoD[d - 1];
+        }
+        tD[0] = TensorRaw<S>::pack(c.t);
+        rhoD[0] = c.rho;
+        fD = (fD << 8) | c.f;
+
+        float xnu[N], xbnu[N];
+        float2 xnv[N], xbnv[N], ynp[N];
+        float4 ynq[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int lo = y0 - (N - 1 - i), hi = y1 + (N - 1 - i);
+            const int q = r + i;
+            const float u_in = i == 0 ? c.u : xu[i - 1];
+            const float2 v_in = i == 0 ? c.v : xv[i - 1];
+            const float2 p_in = i == 0 ? c.p : yp[i - 1];
+            const float4 q_in = i == 0 ? c.q : yq[i - 1];
+            const float4 t_q = i == 0 ? c.t : TensorRaw<S>::unpack(tD[i]);
+            const Above ab = i == 0 ? above_of(nx.p, nx.q, nx.t, nx.f)
+                                    : above_of(ynp[i - 1], ynq[i - 1], TensorRaw<S>::unpack(tD[i - 1]), flag(i - 1));
+            xnu[i] = 0.f;
+            xnv[i] = make_float2(0.f, 0.f);
+            xbnu[i] = 0.f;
+            xbnv[i] = make_float2(0.f, 0.f);
+            if (q >= lo && q <= hi) {
+                float un;
+                float2 vn;
+                primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[i], flag(i), ab, a0, a1, lam, a.tau_n[i], un, vn);
+                const float th = a.theta_n[i];
+                xnu[i] = un;
+                xnv[i] = vn;
+                xbnu[i] = un + th * (un - u_in);
+                xbnv[i] = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
+                if (i == N - 1 && owner && q >= y0 && q < y1) {
+                    const size_t o = (size_t)q * P.pitch + x;
+                    P.u_out[o] = un;
+                    if (TGV) P.v_out[o] = vn;
+                }
+            }
+            ynp[i] = make_float2(0.f, 0.f);
+            ynq[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (q >= lo && q <= hi - 1) {
+                const float ub_r = from_right(xbnu[i]);
+                const float2 vb_r = make_float2(from_right(xbnv[i].x), from_right(xbnv[i].y));
+                dual_step<TGV>(p_in, q_in, t_q, flag(i), xbnu[i], xbnv[i], ub_r, vb_r, xbu[i], xbv[i], a0, a1,
+                               a.sigma_n[i], ynp[i], ynq[i]);
+                if (i == N - 1 && owner && q >= y0 && q < y1) {
+                    const size_t o = (size_t)q * P.pitch + x;
+                    st2<S>(P.p_out, o, ynp[i]);
+                    if (TGV) st4<S>(P.q_out, o, ynq[i]);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            xu[i] = xnu[i];
+            xv[i] = xnv[i];
+            xbu[i] = xbnu[i];
+            xbv[i] = xbnv[i];
+            yp[i] = ynp[i];
+            yq[i] = ynq[i];
+        }
+        c = nx;
+    }
+}
+
+// N iterations in one pass over memory.  Even segments march down, odd ones
+// up, so that the halo rows two neighbouring segments share are read by both
+// at the same time (both at the end of their marches, or both at the start)
+// and the second read hits in L2.  Both marches call the same step functions
+// on the same inputs, so each pixel's result does not depend on the
+// direction (this file contracts multiply-adds only within one expression).
+template <bool TGV, int S, int N>
+__global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) void pdn_kernel(PdArgs a, int by,
+                                                                                               int segs)
+{
+    constexpr int kColsN = kLanes - 2 * N;
+    Task tk;
+    if (!task_of(a, kColsN, by, segs, tk)) return;
+    Planes P;
+    if (!planes_of<S>(a, tk.pair, P)) return;
+    const int tx = tk.tx;
+    if (tx * kColsN >= P.W) return;
+
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int x = tx * kColsN - N + lane;
+    const bool in_x = x >= 0 && x < P.W;
+    const bool owner = lane >= N && lane < N + kColsN && in_x;
+    const int y0 = tk.y0;
+    if (y0 >= P.H) return;
+    const int y1 = min(y0 + by, P.H);
+    if ((y0 / by) & 1)
+        march_up<TGV, S, N>(a, P, x, in_x, owner, y0, y1);
+    else
+        march_down<TGV, S, N>(a, P, x, in_x, owner, y0, y1);
 }
 
 // Wavefronts of a kernel that the current device holds at once (its
