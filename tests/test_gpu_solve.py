@@ -173,3 +173,32 @@ def test_batched_launch_equals_single_pairs(vfs):
     assert torch.equal(o16[3]["u"], s16["u"])
     for a in o16:
         assert torch.isfinite(a["u"]).all() and torch.isfinite(a["w"]).all()
+
+
+@pytest.mark.parametrize("cid,n,check", [("c1", 32, (0, 17, 31)), ("r200", 5, (0, 4))])
+def test_largest_and_ragged_batches(vfs, cid, n, check):
+    """The largest batch (32 pairs, the ABI's limit) and a batch on the ragged
+    200x136 rig: each pair's result equals its single-pair solve bitwise; an
+    empty batch and one past the limit are rejected."""
+    import torch
+    cfg = configs.get(cid)
+    rig = scene.make_rig(cfg)
+    params = configs.solver_params(cfg, warps=2, iters=12)
+    H, W = cfg["height"], cfg["width"]
+    pairs = [_cheap_pair(H, W, 0.5 + 0.1 * b, 300 + b) for b in range(n)]
+    R = vfs.Rig(rig["cam0"], rig["cam1"], rig["R"], rig["t"], params["levels"])
+    I0s = [_t(p[0]) for p in pairs]
+    I1s = [_t(p[1]) for p in pairs]
+    outs = vfs.solve_batch(R, I0s, I1s, params)
+    torch.cuda.synchronize()
+    for b in check:
+        single = vfs.solve(R, I0s[b], I1s[b], params)
+        for k in ("u", "w", "depth", "valid"):
+            assert torch.equal(outs[b][k], single[k]), (b, k)
+    for o in outs:
+        assert torch.isfinite(o["u"]).all() and torch.isfinite(o["w"]).all()
+    with pytest.raises(vfs.VfsError, match="n must be"):
+        vfs.solve_batch(R, [], [], params)
+    if n == 32:
+        with pytest.raises(vfs.VfsError, match="n must be"):
+            vfs.solve_batch(R, I0s + I0s[:1], I1s + I1s[:1], params)
