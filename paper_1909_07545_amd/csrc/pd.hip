@@ -197,7 +197,7 @@ __device__ inline float resolvent(float uhat, float rho, float Iu, float tau, fl
     if (rb < -aI) return uhat + a;
     if (rb > aI) return uhat - a;
     if (Iu == 0.f) return uhat;
-    return uhat - rb / Iu;
+    return uhat - rb * frcp(Iu);
 }
 
 // Primal step at one pixel: x^k from x^{k-1} = (u, v) and y^k = (p, q) at the
@@ -237,11 +237,13 @@ __device__ inline void primal_step(float u, float2 v, float2 p, float4 q, float4
 
 // Dual step at one pixel of row s: y^{k+1} from y^k = (p, q) and xbar^k at
 // the pixel (ub, vb), its right neighbour (ub_r, vb_r; shifted by the caller)
-// and the row below (ub_d, vb_d).  The duals stay as they are outside the mask.
+// and the row below (ub_d, vb_d).  ss scales the step of p; sq is the step of
+// q, ss / (2 alpha0), computed once per march by the caller.  The duals stay
+// as they are outside the mask.
 template <bool TGV>
 __device__ inline void dual_step(float2 p, float4 q, float4 t, unsigned f, float ub, float2 vb, float ub_r,
-                                 float2 vb_r, float ub_d, float2 vb_d, float a0, float a1, float ss, float2& pn,
-                                 float4& qn)
+                                 float2 vb_r, float ub_d, float2 vb_d, float a0, float a1, float ss, float sq,
+                                 float2& pn, float4& qn)
 {
     pn = p;
     qn = q;
@@ -264,7 +266,6 @@ __device__ inline void dual_step(float2 p, float4 q, float4 t, unsigned f, float
     }
     pn = make_float2(p1, p2);
     if (TGV) {
-        const float sq = ss / (2.f * a0);
         float q1 = q.x + sq * a0 * pmx * (vb_r.x - vb.x);
         float q2 = q.y + sq * a0 * pmy * (vb_d.x - vb.x);
         float q3 = q.z + sq * a0 * pmx * (vb_r.y - vb.y);
@@ -326,6 +327,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a, int by, i
     if (y0 >= P.H) return;
     const int y1 = min(y0 + by, P.H);           // owned rows [y0, y1)
     const float a0 = a.alpha0, a1 = a.alpha1;
+    const float sq1 = a.sigma_scale / (2.f * a0);   // the step of q, once per march
 
     // row r - 1 as the dual step needs it
     float2 p_prev = make_float2(0.f, 0.f);
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a, int by, i
                 float2 pn;
                 float4 qn;
                 dual_step<TGV>(p_prev, q_prev, t_prev, f_prev, ub_prev, vb_prev, ub_r, vb_r, ub, vb, a0, a1,
-                               a.sigma_scale, pn, qn);
+                               a.sigma_scale, sq1, pn, qn);
                 const size_t o = (size_t)(r - 1) * P.pitch + x;
                 st2<S>(P.p_out, o, pn);
                 if (TGV) st4<S>(P.q_out, o, qn);
@@ -419,6 +421,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
     if (y0 >= P.H) return;
     const int y1 = min(y0 + by, P.H);
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
+    const float sq1 = a.sigma_scale / (2.f * a0), sq2 = a.sigma_scale2 / (2.f * a0);
 
     // iteration 1: "above" of row r-1, and row r-1 as B needs it
     Above ab1;
@@ -471,7 +474,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
             const float ub_r = from_right(ub1_m1);
             const float2 vb_r = make_float2(from_right(vb1_m1.x), from_right(vb1_m1.y));
             dual_step<TGV>(p_m1, q_m1, t_m1, f_m1, ub1_m1, vb1_m1, ub_r, vb_r, ub1, vb1, a0, a1, a.sigma_scale,
-                           p1, q1);
+                           sq1, p1, q1);
         }
         // C: iteration-2 primal at row r-2 -> x^{k+1}(r-2)
         float ub2 = 0.f;
@@ -496,7 +499,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
             float2 pn;
             float4 qn;
             dual_step<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1, a.sigma_scale2,
-                           pn, qn);
+                           sq2, pn, qn);
             if (owner) {
                 const size_t o = (size_t)(r - 3) * P.pitch + x;
                 st2<S>(P.p_out, o, pn);
@@ -574,6 +577,9 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
 {
     constexpr int D = 2 * N;    // depth of the constants' delay line
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
+    float sqn[N];   // the steps of q, once per march
+#pragma unroll
+    for (int i = 0; i < N; ++i) sqn[i] = a.sigma_n[i] / (2.f * a0);
 
     // constants of rows r - d (d = 0 .. D-1) after the shift of step r: the
     // tensor pack as stored (16-bit modes keep it packed until use), rho_c,
@@ -686,7 +692,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
                 const float ub_r = from_right(xbu[i]);
                 const float2 vb_r = make_float2(from_right(xbv[i].x), from_right(xbv[i].y));
                 dual_step<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, xbnu[i], xbnv[i], a0, a1,
-                               a.sigma_n[i], ynp[i], ynq[i]);
+                               a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
                 if (i == N - 1 && owner && dr >= y0 && dr < y1) {
                     const size_t o = (size_t)dr * P.pitch + x;
                     st2<S>(P.p_out, o, ynp[i]);
@@ -724,6 +730,9 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
                                          int y1)
 {
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
+    float sqn[N];   // the steps of q, once per march
+#pragma unroll
+    for (int i = 0; i < N; ++i) sqn[i] = a.sigma_n[i] / (2.f * a0);
     // constants of rows r + d (d = 0 .. N-1) after the shift of step r
     using TRaw = typename TensorRaw<S>::type;
     TRaw tD[N];
@@ -802,7 +811,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
                 const float ub_r = from_right(xbnu[i]);
                 const float2 vb_r = make_float2(from_right(xbnv[i].x), from_right(xbnv[i].y));
                 dual_step<TGV>(p_in, q_in, t_q, flag(i), xbnu[i], xbnv[i], ub_r, vb_r, xbu[i], xbv[i], a0, a1,
-                               a.sigma_n[i], ynp[i], ynq[i]);
+                               a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
                 if (i == N - 1 && owner && q >= y0 && q < y1) {
                     const size_t o = (size_t)q * P.pitch + x;
                     st2<S>(P.p_out, o, ynp[i]);
