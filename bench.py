@@ -37,6 +37,7 @@ BYTES_PER_PIX_LAUNCH = 93
 BYTES_PER_PIX_LAUNCH_16 = 61
 TEXTBOOK_BYTES_PER_PIX_ITER = 117
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_LANE_INSTR_S = 256 * 4 * 16 * 2.4e9
 
 
 def log(*a):
@@ -146,6 +147,18 @@ def main():
                 "effective_textbook_GBs": round(effective, 1),
                 "level0_Mpix_iter_s": round(iters_per_launch * W * H * n / avg_launch_s / 1e6, 1)}
 
+    # The same launch against the vector-issue peak: a wave64 vector
+    # instruction occupies one of 256 CUs x 4 SIMDs of 16 lanes for 4 cycles at
+    # 2.4 GHz (packed FP32 instructions are not used), i.e. 39.3 T lane-instructions/s.
+    valu = measured_valu(args.config)
+    alu = None
+    if valu is not None and pd_launches:
+        peak_li = VALU_PEAK_LANE_INSTR_S / 1e12
+        achieved_li = valu * 64 / avg_launch_s / 1e12
+        alu = {"bound": "alu", "achieved": round(achieved_li, 2), "peak": round(peak_li, 2),
+               "unit": "T lane-instructions/s", "frac": round(achieved_li / peak_li, 4),
+               "valu_wave64_per_launch": valu, "source": "profiles/pdn3_kernel_batch2048_valu.json"}
+
     fp16 = None
     if not args.no_fp16:
         p16 = dict(params, storage=1)
@@ -195,6 +208,7 @@ def main():
                    "pairs": n, "width": W, "height": H, "levels": cfg["levels"], "warps": cfg["warps"],
                    "iters": cfg["iters"], "pix_iter_per_step": pix_iter},
         "roofline": roofline,
+        "alu": alu,
         "cpu_baseline": cpu,
         "fp16_storage": fp16,
         "serving": serve,
@@ -322,6 +336,21 @@ def serving_study(args, log_prefix="serving"):
     res["batched_config"] = {"hbm_budget_GiB": args.serve_budget_gib, "max_slots_per_size": args.serve_slots,
                              "graphs": True, "storage": "fp16"}
     return res
+
+
+def measured_valu(config):
+    """Wave64 vector instructions per launch of the dominant kernel from the
+    committed rocprofv3 counter summary (SQ_INSTS_VALU), or None if there is
+    none for this workload or the kernel source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pdn3_kernel_batch2048_valu.json")
+    if config != "c5" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1909_07545_amd", "csrc", "pd.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != rec["pd_hip_sha256_prefix"]:
+        return None
+    return rec["valu_wave64_instructions_per_launch"]
 
 
 def measured_traffic(config):
