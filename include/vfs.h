@@ -57,12 +57,14 @@ typedef enum {
 } vfs_model;
 typedef enum { VFS_TGV = 0, VFS_TV = 1 } vfs_reg;
 /* Image the data term compares (Sec. III-A allows any image I): the
- * intensities, or at every pyramid level the rank transform of the level's
+ * intensities; or at every pyramid level the rank transform of the level's
  * images (the share of the 5x5 neighbours strictly darker than the pixel; a
  * census variant, unchanged by any increasing change of the intensities,
- * e.g. gain, offset, gamma).  The tensor of Eq. (12) keeps the intensities.
- * The rank image's contrast calls for a smaller lambda (about 15). */
-typedef enum { VFS_DATA_BRIGHTNESS = 0, VFS_DATA_RANK = 1 } vfs_data_term;
+ * e.g. gain, offset, gamma); or the gradient magnitude of the level's images
+ * (sqrt(Ix^2 + Iy^2), central differences; gradient constancy, unchanged by
+ * an added constant).  The tensor of Eq. (12) keeps the intensities.  Both
+ * transformed images call for their own lambda (rank: about 15). */
+typedef enum { VFS_DATA_BRIGHTNESS = 0, VFS_DATA_RANK = 1, VFS_DATA_GRADIENT = 2 } vfs_data_term;
 /* Storage of the dual variables and of the tensor pack (T^(1/2) of Eq. (12)
  * and I_u): 32-bit float, IEEE half or bfloat16; every update is computed in
  * FP32 and u, v, rho_c stay FP32 (rho_c is formed from I_u as stored). */
@@ -189,14 +191,21 @@ vfs_status vfs_step_tensor(int width, int height, size_t pitch, const float* J0,
 vfs_status vfs_step_rank(int width, int height, size_t pitch, const float* I0, const float* I1, float* R0,
                          float* R1, void* hip_stream);
 
+/* Gradient magnitudes (VFS_DATA_GRADIENT) of two planes: G = sqrt(Ix^2 +
+ * Iy^2) with Ix = (I(x+1) - I(x-1)) / 2 and likewise Iy, neighbours outside
+ * the plane taken at the nearest edge pixel.  Same arguments, layout and
+ * errors as vfs_step_rank. */
+vfs_status vfs_step_gradient(int width, int height, size_t pitch, const float* I0, const float* I1, float* G0,
+                             float* G1, void* hip_stream);
+
 /* Eqs. (3), (5), Sec. III-B, Algorithm 1: with clip != 0 first clip and
  * accumulate the previous warp (du = clamp(u - u_w, +-du_max), u = u_w + du,
  * w += du gamma_w); then (unless clip_only) linearise at y = x + w:
  * gamma_w = bicubic (Keys, a = -1/2) sample g of the trajectory field over
  * max(|g|, 1/2) (unit length except next to an epipole), I_u = I1(y +
  * gamma_w) - I1(y) into tpack.w, rho_c = I1(y) - I0(x) - u I_u, both 0
- * where the data term is off (flags bit3); u_w = u.  With the rank data
- * term the solver passes rank planes as J0, J1. */
+ * where the data term is off (flags bit3); u_w = u.  With the rank or
+ * gradient data term the solver passes those planes as J0, J1. */
 vfs_status vfs_step_linearise(int width, int height, size_t pitch, const float* J0, const float* J1,
                               const float* gamma, const uint8_t* flags, float* u, float* u_w, float* w,
                               float* gamma_w, float* tpack, float* rho, int clip, int clip_only,

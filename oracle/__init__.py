@@ -47,6 +47,9 @@ oracle itself; the tests named live in ``tests/``):
   camera centres, and plausible wrong rotations do not; the round trip
   returns a smooth image; a pinhole camera is its own view
   (test_oracle_rectify).
+* ``gradient_magnitude`` -- equals its definition in plain loops; exact
+  slope on a linear ramp; invariant under an added constant; transposition
+  (test_oracle_rank).
 * ``rank_transform`` -- equals its definition written out in plain loops,
   ties included; invariant under strictly increasing intensity maps and
   transposition (test_oracle_rank).
@@ -73,7 +76,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2, "kannala_brandt": 2, "unified": 3, "ucm": 3,
           "eucm": 4, "enhanced_unified": 4}
 REGS = {"tgv": 0, "tv": 1}
-DATA_TERMS = {"brightness": 0, "rank": 1}
+DATA_TERMS = {"brightness": 0, "rank": 1, "gradient": 2}
 
 
 class _Camera(ctypes.Structure):
@@ -339,6 +342,16 @@ def rank_transform(I, radius: int = 2):
     H, W = I.shape
     out = np.zeros((H, W))
     lib().or_rank_transform(_p(I), W, H, int(radius), _p(out))
+    return out
+
+
+def gradient_magnitude(I):
+    """sqrt(Ix^2 + Iy^2) with edge-clamped central differences: the data
+    term's image for data_term "gradient"."""
+    I = _d(I)
+    H, W = I.shape
+    out = np.zeros((H, W))
+    lib().or_gradient_magnitude(_p(I), W, H, _p(out))
     return out
 
 

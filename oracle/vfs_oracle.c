@@ -46,7 +46,8 @@ typedef struct {
 typedef struct {
     int levels, warps, iters, reg;
     double lambda, alpha0, alpha1, beta, eta, du_max, theta_gamma;
-    int data_term;      /* 0: brightness, 1: rank transform of radius 2 (census variant) */
+    int data_term;      /* 0: brightness, 1: rank transform of radius 2 (census variant),
+                           2: gradient magnitude */
 } or_params;
 
 /* ------------------------------------------------------------------------ */
@@ -476,6 +477,26 @@ void or_unrectify(const or_camera *cam, const double Rv[9], const or_camera *pin
                 continue;
             dst[o] = or_bilinear(field, Wp, Hp, px, py);
             valid[o] = 1;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradient magnitude (gradient constancy; the paper allows any image I in   */
+/* its data term, Sec. III-A): sqrt(Ix^2 + Iy^2) with central differences    */
+/* (I(x+1) - I(x-1)) / 2, pixels outside the image taken at the nearest edge */
+/* pixel.  Adding a constant to the intensities leaves it unchanged.         */
+/* ------------------------------------------------------------------------ */
+
+void or_gradient_magnitude(const double *I, int W, int H, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            int jl = j > 0 ? j - 1 : 0, jr = j < W - 1 ? j + 1 : W - 1;
+            int iu = i > 0 ? i - 1 : 0, id = i < H - 1 ? i + 1 : H - 1;
+            double gx = 0.5 * (I[(size_t)i * W + jr] - I[(size_t)i * W + jl]);
+            double gy = 0.5 * (I[(size_t)id * W + j] - I[(size_t)iu * W + j]);
+            out[(size_t)i * W + j] = sqrt(gx * gx + gy * gy);
         }
 }
 
@@ -1071,7 +1092,7 @@ int or_solve(const or_camera *c0, const or_camera *c1, const double R[9], const 
 {
     int W = c0->width, H = c0->height, L = pp->levels;
     if (L < 1 || pp->warps < 0 || pp->iters < 0) return OR_E_INVALID;
-    if (pp->data_term != 0 && pp->data_term != 1) return OR_E_INVALID;
+    if (pp->data_term < 0 || pp->data_term > 2) return OR_E_INVALID;
     if (c1->width != W || c1->height != H) return OR_E_INVALID;
     if ((W % (1 << (L - 1))) || (H % (1 << (L - 1)))) return OR_E_INVALID;
     int st = or_camera_check(c0);
@@ -1111,8 +1132,8 @@ int or_solve(const or_camera *c0, const or_camera *c1, const double R[9], const 
     double *gam = malloc(2 * n0 * sizeof(double));
     unsigned char *ml = malloc(n0), *dl = malloc(n0), *el = malloc(n0), *mprev = malloc(n0);
     unsigned char *dv0 = malloc(n0);
-    double *R0 = pp->data_term == 1 ? malloc(n0 * sizeof(double)) : NULL;
-    double *R1 = pp->data_term == 1 ? malloc(n0 * sizeof(double)) : NULL;
+    double *R0 = pp->data_term != 0 ? malloc(n0 * sizeof(double)) : NULL;
+    double *R1 = pp->data_term != 0 ? malloc(n0 * sizeof(double)) : NULL;
     size_t lvl_off = 0;
     for (int l = 0; l < L - 1; ++l) lvl_off += (size_t)(W >> l) * (H >> l);
 
@@ -1128,11 +1149,16 @@ int or_solve(const or_camera *c0, const or_camera *c1, const double R[9], const 
         if (l == 0) memcpy(dv0, dl, n0);
         or_tensor(J0[l], ml, Wl, Hl, pp->beta, pp->eta, T);
         if (R0) {
-            /* rank data term: the linearisation of this level sees the
-               rank transforms of the level's images; the tensor keeps the
-               intensities */
-            or_rank_transform(J0[l], Wl, Hl, 2, R0);
-            or_rank_transform(J1[l], Wl, Hl, 2, R1);
+            /* rank / gradient data term: the linearisation of this level
+               sees the transforms of the level's images; the tensor keeps
+               the intensities */
+            if (pp->data_term == 1) {
+                or_rank_transform(J0[l], Wl, Hl, 2, R0);
+                or_rank_transform(J1[l], Wl, Hl, 2, R1);
+            } else {
+                or_gradient_magnitude(J0[l], Wl, Hl, R0);
+                or_gradient_magnitude(J1[l], Wl, Hl, R1);
+            }
         }
         or_steps(T, ml, Wl, Hl, pp->alpha0, pp->alpha1, pp->reg, sp, tu, tv);
         if (l == L - 1) {

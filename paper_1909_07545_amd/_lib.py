@@ -15,7 +15,7 @@ F_MASK, F_MX, F_MY, F_DATA, F_EPI = 1, 2, 4, 8, 16
 MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2, "kannala_brandt": 2, "unified": 3, "ucm": 3,
           "eucm": 4, "enhanced_unified": 4}
 REGS = {"tgv": 0, "tv": 1}
-DATA_TERMS = {"brightness": 0, "rank": 1}
+DATA_TERMS = {"brightness": 0, "rank": 1, "gradient": 2}
 STATUS = {0: "VFS_OK", -1: "VFS_E_INVALID", -2: "VFS_E_NOMEM", -3: "VFS_E_BUDGET", -4: "VFS_E_MODEL",
           -5: "VFS_E_DEGENERATE", -6: "VFS_E_DEVICE"}
 
@@ -86,6 +86,7 @@ def lib():
         L.vfs_profile_read.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int]
         L.vfs_params_default.argtypes = [_vp]
         L.vfs_step_rank.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
+        L.vfs_step_gradient.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
         L.vfs_rectify_rotations.argtypes = [_vp] * 5
         L.vfs_rectify.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _vp]
         L.vfs_unrectify.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _vp]
@@ -131,7 +132,7 @@ def default_params() -> dict:
     return dict(levels=p.levels, warps=p.warps, iters=p.iters, reg="tgv" if p.reg == 0 else "tv",
                 alpha0=p.alpha0, alpha1=p.alpha1, beta=p.beta, eta=p.eta, du_max=p.du_max,
                 theta_gamma=p.theta_gamma, storage=p.storage, pass_iters=p.pass_iters,
-                data_term="rank" if p.data_term == 1 else "brightness", **{"lambda": p.lam})
+                data_term={v: k for k, v in DATA_TERMS.items()}[p.data_term], **{"lambda": p.lam})
 
 
 def _params(d: dict) -> Params:
@@ -251,6 +252,12 @@ def step_rank(I0, I1, R0, R1, stream=None):
     """Rank transforms of two (H, W) planes into R0, R1 (vfs_step_rank)."""
     H, W = I0.shape
     _check(lib().vfs_step_rank(W, H, W, _ptr(I0), _ptr(I1), _ptr(R0), _ptr(R1), _stream(stream)))
+
+
+def step_gradient(I0, I1, G0, G1, stream=None):
+    """Gradient magnitudes of two (H, W) planes into G0, G1 (vfs_step_gradient)."""
+    H, W = I0.shape
+    _check(lib().vfs_step_gradient(W, H, W, _ptr(I0), _ptr(I1), _ptr(G0), _ptr(G1), _stream(stream)))
 
 
 def step_energy(tpack, rho, flags, u, v, params: dict, stream=None) -> float:

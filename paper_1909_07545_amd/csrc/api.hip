@@ -117,12 +117,12 @@ Geometry make_geometry(int W, int H, int L)
     return g;
 }
 
-PairLayout make_layout(const Geometry& g, int storage, bool tgv, bool rank)
+PairLayout make_layout(const Geometry& g, int storage, bool tgv, bool xform)
 {
     PairLayout y{};
     y.storage = storage;
     y.tgv = tgv;
-    y.rank = rank;
+    y.xform = xform;
     const size_t st = stacked_elems(g), one = plane_elems(g, 0);
     const size_t e2 = storage == ST_F32 ? 8 : 4, e4 = storage == ST_F32 ? 16 : 8;
     size_t at = 0;
@@ -144,7 +144,7 @@ PairLayout make_layout(const Geometry& g, int storage, bool tgv, bool rank)
     y.gw = take(one * 8);
     y.tpack = take(one * e4);
     y.rho = take(one * 4);
-    if (rank) {
+    if (xform) {
         y.R0 = take(one * 4);
         y.R1 = take(one * 4);
     }
@@ -168,8 +168,8 @@ void bind_state(Slot& sl, void* region, const PairLayout& y)
     sl.gw = reinterpret_cast<float2*>(m + y.gw);
     sl.tpack = m + y.tpack;
     sl.rho = reinterpret_cast<float*>(m + y.rho);
-    sl.R0 = y.rank ? reinterpret_cast<float*>(m + y.R0) : nullptr;
-    sl.R1 = y.rank ? reinterpret_cast<float*>(m + y.R1) : nullptr;
+    sl.R0 = y.xform ? reinterpret_cast<float*>(m + y.R0) : nullptr;
+    sl.R1 = y.xform ? reinterpret_cast<float*>(m + y.R1) : nullptr;
 }
 
 void bind_rig(Slot& sl, const vfs_rig* r)
@@ -191,15 +191,15 @@ void Workspace::release()
     cap = 0;
 }
 
-vfs_status ensure_workspace(Workspace& ws, const Geometry& g, int n, int storage, bool tgv, bool rank)
+vfs_status ensure_workspace(Workspace& ws, const Geometry& g, int n, int storage, bool tgv, bool xform)
 {
     bool same = ws.mem && ws.cap >= n && ws.g.L == g.L && ws.lay.storage == storage && ws.lay.tgv == tgv &&
-                ws.lay.rank == rank;
+                ws.lay.xform == xform;
     for (int l = 0; same && l < g.L; ++l) same = ws.g.W[l] == g.W[l] && ws.g.H[l] == g.H[l];
     if (same) return VFS_OK;
     ws.release();
     ws.g = g;
-    ws.lay = make_layout(g, storage, tgv, rank);
+    ws.lay = make_layout(g, storage, tgv, xform);
     const size_t bytes = ws.lay.bytes * size_t(n);
     void* m = nullptr;
     if (hipMalloc(&m, bytes) != hipSuccess) return fail(VFS_E_NOMEM, "workspace of %zu bytes for %d pairs", bytes, n);
@@ -238,7 +238,7 @@ vfs_status check_params(const vfs_params* p)
         return fail(VFS_E_INVALID, "unsupported storage");
     if (p->pass_iters != 0 && (p->pass_iters < 2 || p->pass_iters > 4))
         return fail(VFS_E_INVALID, "pass_iters must be 0 (automatic) or 2, 3, 4");
-    if (p->data_term != VFS_DATA_BRIGHTNESS && p->data_term != VFS_DATA_RANK)
+    if (p->data_term < VFS_DATA_BRIGHTNESS || p->data_term > VFS_DATA_GRADIENT)
         return fail(VFS_E_INVALID, "unknown data term");
     if (!(p->alpha0 > 0.0) || !(p->alpha1 > 0.0) || !(p->lambda >= 0.0) || !(p->du_max > 0.0) ||
         !(p->theta_gamma >= 0.0) || !(p->beta >= 0.0) || !(p->eta > 0.0))
@@ -369,7 +369,7 @@ vfs_status solve_slots(const Slot* slots, int n, const Geometry& g, const vfs_pa
     const int L = g.L;
     const bool tgv = params.reg == VFS_TGV;
     const int st = params.storage;
-    const int rank = params.data_term == VFS_DATA_RANK ? 1 : 0;
+    const int xform = params.data_term;   // 0: the intensities themselves
     Launch lc{};
     lc.slots = slots;
     lc.n = n;
@@ -390,14 +390,14 @@ vfs_status solve_slots(const Slot* slots, int n, const Geometry& g, const vfs_pa
         at(l);
         // A3: tensor of the level (Eq. (12)); A7: state of the level
         launch_tensor(lc, st, s);
-        if (rank) launch_rank(lc, s);
+        if (xform) launch_transform(lc, xform, s);
         if (l == L - 1) launch_zero_state(lc, tgv ? 1 : 0, st, s);
         else launch_upsample(lc, tgv ? 1 : 0, st, s);
         for (int wv = 0; wv <= params.warps; ++wv) {
             // A4 (+A6 of the previous warp): clip, accumulate, linearise
             const bool last = wv == params.warps;
             if (last && wv == 0) break;
-            launch_linearise(lc, wv > 0 ? 1 : 0, last ? 1 : 0, float(params.du_max), rank, st, s);
+            launch_linearise(lc, wv > 0 ? 1 : 0, last ? 1 : 0, float(params.du_max), xform != 0, st, s);
             if (last) break;
             // A5: K primal-dual iterations (Eq. (11))
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -551,7 +551,7 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
             return fail(VFS_E_INVALID, "bad tensor parameters for pair %d", b);
     }
     st = ensure_workspace(r->ws, r->g, n, params->storage, params->reg == VFS_TGV,
-                          params->data_term == VFS_DATA_RANK);
+                          params->data_term != VFS_DATA_BRIGHTNESS);
     if (st) return st;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     r->last_stream = s;
@@ -664,7 +664,27 @@ vfs_status vfs_step_rank(int W, int H, size_t pitch, const float* I0, const floa
     OneSlot os;
     vfs_status st = run_one(os, sl, s);
     if (st) return st;
-    launch_rank(one_launch(os, one_level(W, H, pitch)), s);
+    launch_transform(one_launch(os, one_level(W, H, pitch)), VFS_DATA_RANK, s);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+    return VFS_OK;
+}
+
+vfs_status vfs_step_gradient(int W, int H, size_t pitch, const float* I0, const float* I1, float* G0, float* G1,
+                             void* hip_stream)
+{
+    g_err[0] = 0;
+    if (W <= 0 || H <= 0 || pitch < size_t(W) || !I0 || !I1 || !G0 || !G1) return fail(VFS_E_INVALID, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Slot sl{};
+    sl.J0 = const_cast<float*>(I0);
+    sl.J1 = const_cast<float*>(I1);
+    sl.R0 = G0;
+    sl.R1 = G1;
+    OneSlot os;
+    vfs_status st = run_one(os, sl, s);
+    if (st) return st;
+    launch_transform(one_launch(os, one_level(W, H, pitch)), VFS_DATA_GRADIENT, s);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(s));
     return VFS_OK;

@@ -148,7 +148,7 @@ __global__ void tensor_kernel(Launch lc)
 // the data term compares the level's rank transforms R0, R1 instead of the
 // images themselves (the tensor keeps the intensities).
 template <int S>
-__global__ void linearise_kernel(Launch lc, int clip, int clip_only, float du_max, int rank)
+__global__ void linearise_kernel(Launch lc, int clip, int clip_only, float du_max, int xform)
 {
     Pick pk;
     int j, i;
@@ -187,8 +187,8 @@ __global__ void linearise_kernel(Launch lc, int clip, int clip_only, float du_ma
     sl.gw[o] = g;
     float Iu = 0.f, rc = 0.f;
     if (sl.flags[l][o] & F_DATA) {
-        const float* J1 = rank ? sl.R1 : sl.J1 + off;
-        const float i0 = rank ? sl.R0[o] : sl.J0[os];
+        const float* J1 = xform ? sl.R1 : sl.J1 + off;
+        const float i0 = xform ? sl.R0[o] : sl.J0[os];
         const float i1 = bilinear(J1, pitch, W, H, j, i, ww.x, ww.y);
         const float i1s = bilinear(J1, pitch, W, H, j, i, ww.x + g.x, ww.y + g.y);
         // rho_c is formed from I_u as stored, so that rho_c + u I_u is exact at u = u_w
@@ -205,11 +205,15 @@ __global__ void linearise_kernel(Launch lc, int clip, int clip_only, float du_ma
     sl.rho[o] = rc;
 }
 
-// Rank transform (a census variant): the share of the 5x5 neighbours that are
-// strictly darker than the pixel, neighbours outside the level taken at the
-// nearest edge pixel.  Counts are exact, so the result is that of any
-// correct implementation on the same float inputs.
-__global__ void rank_kernel(Launch lc)
+// The data term's images of a level (into R0, R1):
+//  KIND 1, rank transform (a census variant): the share of the 5x5 neighbours
+//    strictly darker than the pixel; counts are exact, so the result is that
+//    of any correct implementation on the same float inputs;
+//  KIND 2, gradient magnitude: sqrt(Ix^2 + Iy^2), central differences
+//    (I(x+1) - I(x-1)) / 2.
+// Neighbours outside the level are taken at the nearest edge pixel.
+template <int KIND>
+__global__ void transform_kernel(Launch lc)
 {
     Pick pk;
     int j, i;
@@ -217,20 +221,28 @@ __global__ void rank_kernel(Launch lc)
     const Slot& sl = lc.slots[blockIdx.z];
     const int l = pk.l, W = lc.g.W[l], H = lc.g.H[l], pitch = lc.g.pitch[l];
     const long long off = lc.g.off[l];
-    constexpr int r = kRankRadius;
-    constexpr float norm = 1.f / float((2 * r + 1) * (2 * r + 1) - 1);
     const float* img[2] = {sl.J0 + off, sl.J1 + off};
     float* out[2] = {sl.R0, sl.R1};
     for (int k = 0; k < 2; ++k) {
         const float* I = img[k];
-        const float c = I[(size_t)i * pitch + j];
-        int count = 0;
-        for (int di = -r; di <= r; ++di) {
-            const float* row = I + (size_t)clampi(i + di, 0, H - 1) * pitch;
-            for (int dj = -r; dj <= r; ++dj)
-                if (di || dj) count += row[clampi(j + dj, 0, W - 1)] < c;
+        if constexpr (KIND == 1) {
+            constexpr int r = kRankRadius;
+            constexpr float norm = 1.f / float((2 * r + 1) * (2 * r + 1) - 1);
+            const float c = I[(size_t)i * pitch + j];
+            int count = 0;
+            for (int di = -r; di <= r; ++di) {
+                const float* row = I + (size_t)clampi(i + di, 0, H - 1) * pitch;
+                for (int dj = -r; dj <= r; ++dj)
+                    if (di || dj) count += row[clampi(j + dj, 0, W - 1)] < c;
+            }
+            out[k][(size_t)i * pitch + j] = float(count) * norm;
+        } else {
+            const float* row = I + (size_t)i * pitch;
+            const float gx = 0.5f * (row[clampi(j + 1, 0, W - 1)] - row[clampi(j - 1, 0, W - 1)]);
+            const float gy = 0.5f * (I[(size_t)clampi(i + 1, 0, H - 1) * pitch + j] -
+                                     I[(size_t)clampi(i - 1, 0, H - 1) * pitch + j]);
+            out[k][(size_t)i * pitch + j] = sqrtf(gx * gx + gy * gy);
         }
-        out[k][(size_t)i * pitch + j] = float(count) * norm;
     }
 }
 
@@ -384,16 +396,17 @@ void launch_tensor(const Launch& lc, int storage, hipStream_t s)
     VFS_BY_STORAGE(storage, hipLaunchKernelGGL(tensor_kernel<S>, grid_for(lc), dim3(64), 0, s, lc));
 }
 
-void launch_linearise(const Launch& lc, int clip, int clip_only, float du_max, int rank, int storage,
+void launch_linearise(const Launch& lc, int clip, int clip_only, float du_max, int xform, int storage,
                       hipStream_t s)
 {
     VFS_BY_STORAGE(storage, hipLaunchKernelGGL(linearise_kernel<S>, grid_for(lc), dim3(64), 0, s, lc, clip,
-                                               clip_only, du_max, rank));
+                                               clip_only, du_max, xform));
 }
 
-void launch_rank(const Launch& lc, hipStream_t s)
+void launch_transform(const Launch& lc, int kind, hipStream_t s)
 {
-    hipLaunchKernelGGL(rank_kernel, grid_for(lc), dim3(64), 0, s, lc);
+    if (kind == 1) hipLaunchKernelGGL(transform_kernel<1>, grid_for(lc), dim3(64), 0, s, lc);
+    else hipLaunchKernelGGL(transform_kernel<2>, grid_for(lc), dim3(64), 0, s, lc);
 }
 
 void launch_upsample(const Launch& lc, int tgv, int storage, hipStream_t s)

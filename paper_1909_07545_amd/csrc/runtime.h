@@ -27,9 +27,9 @@ struct PairLayout {
     size_t J0, J1, u[2], v[2], p[2], q[2], w, uw, gw, tpack, rho, R0, R1;
     size_t bytes;
     int storage;
-    bool tgv, rank;
+    bool tgv, xform;   // xform: the data term's image planes R0, R1
 };
-PairLayout make_layout(const Geometry& g, int storage, bool tgv, bool rank);
+PairLayout make_layout(const Geometry& g, int storage, bool tgv, bool xform);
 // Points the state fields of sl into region (device memory of lay.bytes).
 void bind_state(Slot& sl, void* region, const PairLayout& lay);
 
@@ -47,7 +47,7 @@ struct Workspace {
     ~Workspace() { release(); }
     void release();
 };
-vfs_status ensure_workspace(Workspace& ws, const Geometry& g, int n, int storage, bool tgv, bool rank);
+vfs_status ensure_workspace(Workspace& ws, const Geometry& g, int n, int storage, bool tgv, bool xform);
 
 }  // namespace vfs
 

@@ -207,7 +207,7 @@ void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int gl, i
     const vfs_params& P = sv->params;
     const bool tgv = P.reg == VFS_TGV;
     const int st = P.storage;
-    const int rank = P.data_term == VFS_DATA_RANK ? 1 : 0;
+    const int xform = P.data_term;   // 0: the intensities themselves
     const int L = b.g.L;
     Launch lc{};
     lc.slots = b.slots_dev;
@@ -233,7 +233,7 @@ void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int gl, i
             lc.op = OP_NEWLEVEL;
             lc.dl = 1;
             lc.gl = gl + 1 < L ? gl + 1 : L - 1;
-            launch_linearise(lc, 1, 1, float(P.du_max), rank, st, s);
+            launch_linearise(lc, 1, 1, float(P.du_max), xform != 0, st, s);
             lc.dl = 0;
             lc.gl = gl;
             launch_upsample(lc, tgv ? 1 : 0, st, s);
@@ -244,12 +244,12 @@ void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int gl, i
         lc.gl = gl;
         lc.op = OP_TENSOR;
         launch_tensor(lc, st, s);
-        if (rank) launch_rank(lc, s);
+        if (xform) launch_transform(lc, xform, s);
     }
     // warp step
     lc.gl = gl;
     lc.op = OP_WARP;
-    launch_linearise(lc, -1, 0, float(P.du_max), rank, st, s);
+    launch_linearise(lc, -1, 0, float(P.du_max), xform != 0, st, s);
     int iu = 0, ip = 0;
     run_pd(pd_args(lc, P), sv->sched, P.iters, iu, ip, s, nullptr, nullptr);
     // finish
@@ -259,7 +259,7 @@ void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int gl, i
         lc.op = OP_FINISH;
         lc.lev = 0;
         lc.gl = 0;
-        launch_linearise(lc, 1, 1, float(P.du_max), rank, st, s);
+        launch_linearise(lc, 1, 1, float(P.du_max), xform != 0, st, s);
         launch_triangulate(lc, s);
     }
     par_u = iu;
@@ -270,7 +270,7 @@ vfs_status make_bucket(vfs_server* sv, const Geometry& g, Bucket*& out)
 {
     auto b = std::make_unique<Bucket>();
     b->g = g;
-    b->lay = make_layout(g, sv->params.storage, sv->params.reg == VFS_TGV, sv->params.data_term == VFS_DATA_RANK);
+    b->lay = make_layout(g, sv->params.storage, sv->params.reg == VFS_TGV, sv->params.data_term != VFS_DATA_BRIGHTNESS);
     b->S = sv->cfg.max_slots;
     b->slot.resize(b->S);
     if (hipMalloc(&b->slots_dev, sizeof(Slot) * b->S) != hipSuccess ||
@@ -503,7 +503,7 @@ bool plain_step(vfs_server* sv)
         sv->plain_ws.push_back(std::make_unique<Workspace>());
         ws = sv->plain_ws.back().get();
         st = ensure_workspace(*ws, r->rig->g, 1, sv->params.storage, sv->params.reg == VFS_TGV,
-                              sv->params.data_term == VFS_DATA_RANK);
+                              sv->params.data_term != VFS_DATA_BRIGHTNESS);
     }
     if (!st && ws->lay.bytes > sv->cfg.hbm_budget_bytes) st = fail(VFS_E_BUDGET, "request exceeds the HBM budget");
     if (st) {
@@ -624,8 +624,8 @@ vfs_status vfs_server_create(const vfs_server_config* cfg, const vfs_params* par
 vfs_status vfs_server_request_bytes(const vfs_server* sv, const vfs_rig* rig, size_t* bytes)
 {
     if (!sv || !rig || !bytes) return fail(VFS_E_INVALID, "NULL argument");
-    *bytes = make_layout(rig->g, sv->params.storage, sv->params.reg == VFS_TGV, sv->params.data_term == VFS_DATA_RANK)
-                 .bytes;
+    const vfs_params& P = sv->params;
+    *bytes = make_layout(rig->g, P.storage, P.reg == VFS_TGV, P.data_term != VFS_DATA_BRIGHTNESS).bytes;
     return VFS_OK;
 }
 
@@ -639,8 +639,8 @@ vfs_status vfs_server_submit(vfs_server* sv, vfs_rig* rig, const float* I0, cons
     const int W = rig->g.W[0];
     if (pitch_bytes % sizeof(float) || pitch_bytes < sizeof(float) * W) return fail(VFS_E_INVALID, "bad pitch");
     if (!(beta >= 0.0) || !(eta > 0.0)) return fail(VFS_E_INVALID, "bad tensor parameters");
-    const size_t need =
-        make_layout(rig->g, sv->params.storage, sv->params.reg == VFS_TGV, sv->params.data_term == VFS_DATA_RANK).bytes;
+    const vfs_params& P = sv->params;
+    const size_t need = make_layout(rig->g, P.storage, P.reg == VFS_TGV, P.data_term != VFS_DATA_BRIGHTNESS).bytes;
     if (sv->cfg.mode == VFS_SERVE_BATCHED && need > sv->cfg.hbm_budget_bytes)
         return fail(VFS_E_BUDGET, "one request needs %zu bytes, the HBM budget is %zu", need,
                     sv->cfg.hbm_budget_bytes);

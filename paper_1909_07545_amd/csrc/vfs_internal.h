@@ -285,8 +285,8 @@ struct Slot {
     float2* gw;
     void* tpack;
     float* rho;
-    float* R0;                  // single-level rank transforms of the level's images
-    float* R1;                  // (rank data term only, else NULL)
+    float* R0;                  // single-level data-term images of the level (rank transform
+    float* R1;                  // or gradient magnitude; brightness data term: NULL)
     float beta, eta;
 };
 
@@ -365,11 +365,11 @@ void launch_write_ctrl(const CtrlBlock& cb, int n, Ctrl* dst, hipStream_t s);
 void launch_prerotate(const Launch& lc, hipStream_t s);                      // J1[0], J0[0] of level 0
 void launch_downsample(const Launch& lc, hipStream_t s);                     // J0, J1 level lev from lev - 1
 void launch_tensor(const Launch& lc, int storage, hipStream_t s);
-void launch_linearise(const Launch& lc, int clip, int clip_only, float du_max, int rank, int storage,
+void launch_linearise(const Launch& lc, int clip, int clip_only, float du_max, int xform, int storage,
                       hipStream_t s);
 // Rank transform (radius 2) of the level's J0, J1 into R0, R1.
 constexpr int kRankRadius = 2;
-void launch_rank(const Launch& lc, hipStream_t s);
+void launch_transform(const Launch& lc, int kind, hipStream_t s);   // kind: vfs_data_term (1, 2)
 void launch_upsample(const Launch& lc, int tgv, int storage, hipStream_t s);  // level + 1 -> level
 void launch_zero_state(const Launch& lc, int tgv, int storage, hipStream_t s);
 void launch_triangulate(const Launch& lc, hipStream_t s);                    // level 0

@@ -15,11 +15,11 @@ by pytest; it needs a GPU and a few minutes of host CPU).
       oracle.
 
   python -m tests.accuracy_study data_term OUT.json
-      Brightness-constancy against rank-transform data term on rendered
-      scenes with ground truth (the 128x128 plane, 4 pairs of the 640x480
-      Kannala-Brandt room): unchanged images, I1 through a strictly
-      increasing intensity curve, and I1 under a radial gain (vignetting of
-      camera 1 only).  Error of x + w against the rendered correspondence
+      Brightness-constancy against the rank-transform and gradient-magnitude
+      data terms on rendered scenes with ground truth (the 128x128 plane, 4
+      pairs of the 640x480 Kannala-Brandt room): unchanged images, I1 through
+      a strictly increasing intensity curve, I1 under a radial gain
+      (vignetting of camera 1 only), and I1 plus a constant.  Error of x + w against the rendered correspondence
       over pixels whose data term is on and that camera 1 sees.
 
   python -m tests.accuracy_study rectified OUT.json
@@ -158,8 +158,12 @@ def data_term():
         r2 = ((jj - cam["cx"]) ** 2 + (ii - cam["cy"]) ** 2) / (0.25 * (W * W + H * H))
         return I * (1.0 - 0.45 * r2)
 
-    changes = {"none": None, "curve": curve, "vignette": vignette}
-    terms = [("brightness", configs.PAPER_PARAMS["lambda"])] + [("rank", lam) for lam in (2.0, 5.0, 15.0, 30.0)]
+    def offset(I, cam):
+        return I + 0.15
+
+    changes = {"none": None, "curve": curve, "vignette": vignette, "offset": offset}
+    terms = ([("brightness", configs.PAPER_PARAMS["lambda"])] + [("rank", lam) for lam in (2.0, 5.0, 15.0, 30.0)] +
+             [("gradient", lam) for lam in (15.0, 50.0)])
     rows = []
     for cid, pairs in (("c1", 1), ("c2", 4)):
         cfg = configs.get(cid)

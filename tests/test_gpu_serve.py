@@ -103,7 +103,8 @@ def _assert_equal(a, b, tag):
 
 
 @pytest.mark.parametrize("iters,storage,data_term", [(4, 1, "brightness"), (5, 1, "brightness"), (6, 1, "brightness"),
-                                                     (4, 0, "brightness"), (5, 0, "brightness"), (5, 1, "rank")])
+                                                     (4, 0, "brightness"), (5, 0, "brightness"), (5, 1, "rank"),
+                                                     (4, 1, "gradient")])
 def test_mix_equals_alone(workload, iters, storage, data_term):
     import paper_1909_07545_amd as vfs
     params = _params(iters, storage, data_term)

@@ -98,14 +98,16 @@ def _assert_floor(r):
     ("c1", dict(levels=1, warps=2, iters=1)), ("c1", dict(iters=0)), ("r200", dict(warps=1, reg="tv")),
     ("ucm", dict(warps=1)), ("eucm", dict(warps=1)),
     ("c1", dict(warps=1, data_term="rank", **{"lambda": 2.0})),
-    ("r200", dict(warps=1, data_term="rank", **{"lambda": 15.0}))])
+    ("r200", dict(warps=1, data_term="rank", **{"lambda": 15.0})),
+    ("c1", dict(warps=1, data_term="gradient")), ("r200", dict(warps=1, data_term="gradient"))])
 def test_short_schedules_meet_the_fp32_bar(vfs, cid, ov):
     _assert_bar(_run(vfs, cid, **ov))
 
 
 @pytest.mark.parametrize("cid,ov", [
     ("c1", {}), ("c1", dict(reg="tv")), ("r200", {}), ("r200", dict(theta_gamma=0.2)), ("c2", {}), ("ucm", {}),
-    ("eucm", {}), ("c1", dict(data_term="rank", **{"lambda": 2.0})), ("r200", dict(data_term="rank", **{"lambda": 15.0}))])
+    ("eucm", {}), ("c1", dict(data_term="rank", **{"lambda": 2.0})), ("r200", dict(data_term="rank", **{"lambda": 15.0})),
+    ("c1", dict(data_term="gradient"))])
 def test_full_schedules_within_conditioning_floor(vfs, cid, ov):
     _assert_floor(_run(vfs, cid, floor=True, **ov))
 

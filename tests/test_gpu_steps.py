@@ -172,6 +172,21 @@ def test_rank(vfs, H, W):
         assert np.max(np.abs(g - np.rint(g))) < 1e-5
 
 
+@pytest.mark.parametrize("H,W", [(128, 128), (136, 200), (1, 7), (3, 2), (2048, 2048)])
+def test_gradient(vfs, H, W):
+    """Gradient magnitude (central differences, edges clamped): float32 vs
+    FP64 on the same float32 inputs within 1e-6 (values up to about 1)."""
+    import torch
+    rng = np.random.default_rng(H * 5 + W)
+    I0 = _smooth_image(H, W, 13) if min(H, W) > 8 else rng.random((H, W)).astype(np.float32)
+    I1 = rng.random((H, W)).astype(np.float32)
+    G0 = torch.full((H, W), float("nan"), device="cuda")
+    G1 = torch.full((H, W), float("nan"), device="cuda")
+    vfs.step_gradient(_t(I0), _t(I1), G0, G1)
+    for got, I in ((G0, I0), (G1, I1)):
+        assert np.max(np.abs(_np(got).astype(np.float64) - oracle.gradient_magnitude(f32(I)))) < 1e-6
+
+
 def _pd_state(cid, level, tgv=True, seed=5):
     rig, flags, J0, _, _ = _level_inputs(cid, level, seed=seed)
     H, W = J0.shape

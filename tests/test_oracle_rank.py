@@ -1,5 +1,5 @@
-"""Pins of the oracle's rank-transform data term (a census variant; the paper
-allows any image in its data term, Sec. III-A).
+"""Pins of the oracle's rank-transform (a census variant) and gradient-magnitude
+data terms (the paper allows any image in its data term, Sec. III-A).
 
 - The transform against its definition written out in plain Python loops on
   small images, ties included.
@@ -82,3 +82,54 @@ def test_rank_data_term_survives_an_illumination_change():
     assert tau_b < 0.01 and tau_bc > 0.5             # brightness constancy broken by the change
     assert tau_r < 0.01 and tau_rc < 0.01            # the rank term does not see it
     assert abs(epe_rc - epe_r) <= 0.05 * epe_r and epe_r < 0.1
+
+
+def _gradient_by_definition(I):
+    H, W = I.shape
+    out = np.zeros((H, W))
+    for i in range(H):
+        for j in range(W):
+            gx = 0.5 * (I[i, min(j + 1, W - 1)] - I[i, max(j - 1, 0)])
+            gy = 0.5 * (I[min(i + 1, H - 1), j] - I[max(i - 1, 0), j])
+            out[i, j] = np.sqrt(gx * gx + gy * gy)
+    return out
+
+
+def test_gradient_magnitude_pins():
+    """Against the definition in plain loops; a linear ramp gives its slope
+    exactly inside the image; an added constant changes nothing; transposing
+    the image transposes the result."""
+    rng = np.random.default_rng(21)
+    for shape in ((7, 9), (1, 5), (4, 1), (13, 6)):
+        I = rng.random(shape)
+        assert np.max(np.abs(oracle.gradient_magnitude(I) - _gradient_by_definition(I))) < 1e-15
+    jj, ii = np.meshgrid(np.arange(20.0), np.arange(15.0))
+    G = oracle.gradient_magnitude(0.03 * jj - 0.04 * ii + 0.2)
+    assert np.max(np.abs(G[1:-1, 1:-1] - 0.05)) < 1e-15
+    I = rng.random((30, 41))
+    assert np.max(np.abs(oracle.gradient_magnitude(I + 0.25) - oracle.gradient_magnitude(I))) < 1e-15
+    assert np.array_equal(oracle.gradient_magnitude(I.T.copy()), oracle.gradient_magnitude(I).T)
+
+
+def test_gradient_data_term_survives_an_offset():
+    """The whole method on the 128x128 plane with I1 + 0.15: the gradient data
+    term recovers the rendered correspondences as without the offset; the
+    brightness data term does not."""
+    d = inputs("c1")
+    rig, cfg = d["rig"], d["cfg"]
+    I0 = d["I0"][0].astype(np.float64)
+    I1 = d["I1"][0].astype(np.float64)
+    gt = d["gt"][0]
+    res = {}
+    for term, lam in (("brightness", 50.0), ("gradient", 50.0)):
+        for off in (0.0, 0.15):
+            params = configs.solver_params(cfg, data_term=term, **{"lambda": lam})
+            o = oracle.solve(rig["cam0"], rig["cam1"], rig["R"], rig["t"], params, I0, I1 + off)
+            keep = oracle.mask0(rig["cam0"]).astype(bool) & gt["visible"] & (o["valid"] > 0)
+            e = np.linalg.norm(o["w"] - gt["flow"], axis=-1)[keep]
+            res[(term, off)] = (float(np.mean(e > 1.0)), float(np.median(e)))
+    print(res)
+    assert res[("brightness", 0.15)][0] > 0.5
+    assert res[("gradient", 0.0)][0] < 0.05 and res[("gradient", 0.15)][0] < 0.05
+    # the offset changes the pyramid only by the same constant: nothing moves
+    assert abs(res[("gradient", 0.15)][1] - res[("gradient", 0.0)][1]) < 1e-9
