@@ -175,12 +175,20 @@ struct Above {
     float b, cy, my, myq2, myq4;
 };
 
+// The parts of a row's "above" contribution that the step sizes need (they
+// depend on the tensor and the mask bits only).
+__device__ inline void above_steps(float4 t, unsigned f, float& cy, float& my)
+{
+    my = (f & F_MY) ? 1.f : 0.f;
+    cy = my * (fabsf(t.y) + fabsf(t.z));
+}
+
 __device__ inline Above above_of(float2 p, float4 q, float4 t, unsigned f)
 {
     Above ab;
-    const float my = (f & F_MY) ? 1.f : 0.f;
+    float my;
+    above_steps(t, f, ab.cy, my);
     ab.b = my * (t.y * p.x + t.z * p.y);
-    ab.cy = my * (fabsf(t.y) + fabsf(t.z));
     ab.my = my;
     ab.myq2 = my * q.y;
     ab.myq4 = my * q.w;
@@ -200,33 +208,68 @@ __device__ inline float resolvent(float uhat, float rho, float Iu, float tau, fl
     return uhat - rb * frcp(Iu);
 }
 
+// Step sizes of the diagonal preconditioning (Sec. III-D) at a pixel, before
+// an iteration's schedule factor: the primal steps of u and v from the
+// pixel's tensor and mask bits, its left neighbour's (lane shifts; every lane
+// of the wavefront calls this) and the row above's (cy, my of above_steps).
+struct PrimalBases {
+    float tu, tv;
+};
+
+template <bool TGV>
+__device__ inline PrimalBases primal_bases(float4 t, unsigned f, float cy_up, float my_up, float a0, float a1)
+{
+    const float mx = (f & F_MX) ? 1.f : 0.f;
+    const float my = (f & F_MY) ? 1.f : 0.f;
+    const float cx = mx * (fabsf(t.x) + fabsf(t.y));
+    const float cx_l = from_left(cx);
+    const float cu = fabsf(t.x * mx + t.y * my) + fabsf(t.y * mx + t.z * my) + cx_l + cy_up;
+    PrimalBases b;
+    b.tu = cu > 0.f ? frcp(a1 * cu) : frcp(a1);
+    b.tv = 0.f;
+    if (TGV) {
+        const float mx_l = from_left(mx);
+        b.tv = frcp(a1 + a0 * (mx + my + mx_l + my_up));
+    }
+    return b;
+}
+
+// The dual step of p at a pixel, before an iteration's schedule factor.
+template <bool TGV>
+__device__ inline float dual_base(float4 t, unsigned f, float a1)
+{
+    const float pmx = (f & F_MX) ? 1.f : 0.f;
+    const float pmy = (f & F_MY) ? 1.f : 0.f;
+    const float vrow = TGV ? a1 : 0.f;
+    const float s1 = a1 * (fabsf(t.x * pmx + t.y * pmy) + fabsf(t.x) * pmx + fabsf(t.y) * pmy) + vrow;
+    const float s2 = a1 * (fabsf(t.y * pmx + t.z * pmy) + fabsf(t.y) * pmx + fabsf(t.z) * pmy) + vrow;
+    const float smax = fmaxf(s1, s2);
+    return smax > 0.f ? frcp(smax) : frcp(a1);
+}
+
 // Primal step at one pixel: x^k from x^{k-1} = (u, v) and y^k = (p, q) at the
-// pixel, its left neighbour (lane shifts) and the row above (ab).  Called by
-// every lane of the wavefront (it shifts across lanes).  Returns (un, vn);
-// the pixel is left unchanged outside the mask.
+// pixel, its left neighbour (lane shifts) and the row above (ab), with the
+// steps tau_u, tau_v (bases times the iteration's factor).  Called by every
+// lane of the wavefront (it shifts across lanes).  Returns (un, vn); the pixel
+// is left unchanged outside the mask.
 template <bool TGV>
 __device__ inline void primal_step(float u, float2 v, float2 p, float4 q, float4 t, float rho, unsigned f,
-                                   const Above& ab, float a0, float a1, float lambda, float ts, float& un,
-                                   float2& vn)
+                                   const Above& ab, float a0, float a1, float lambda, float tau_u, float tau_v,
+                                   float& un, float2& vn)
 {
     const float mx = (f & F_MX) ? 1.f : 0.f;
     const float my = (f & F_MY) ? 1.f : 0.f;
     const float ax = mx * (t.x * p.x + t.y * p.y);
-    const float cx = mx * (fabsf(t.x) + fabsf(t.y));
     const float ax_l = from_left(ax);
-    const float cx_l = from_left(cx);
     const float b = my * (t.y * p.x + t.z * p.y);
     const float divtp = ax - ax_l + b - ab.b;
-    const float cu = fabsf(t.x * mx + t.y * my) + fabsf(t.y * mx + t.z * my) + cx_l + ab.cy;
-    const float tau_u = (cu > 0.f ? frcp(a1 * cu) : frcp(a1)) * ts;
     const float ur = resolvent(u + tau_u * a1 * divtp, rho, t.w, tau_u, lambda);
     float2 vr = v;
     if (TGV) {
         const float mxq1 = mx * q.x, mxq3 = mx * q.z;
-        const float mxq1_l = from_left(mxq1), mxq3_l = from_left(mxq3), mx_l = from_left(mx);
+        const float mxq1_l = from_left(mxq1), mxq3_l = from_left(mxq3);
         const float d1 = mxq1 - mxq1_l + my * q.y - ab.myq2;
         const float d2 = mxq3 - mxq3_l + my * q.w - ab.myq4;
-        const float tau_v = frcp(a1 + a0 * (mx + my + mx_l + ab.my)) * ts;
         vr.x = v.x + tau_v * (a1 * p.x + a0 * d1);
         vr.y = v.y + tau_v * (a1 * p.y + a0 * d2);
     }
@@ -237,12 +280,12 @@ __device__ inline void primal_step(float u, float2 v, float2 p, float4 q, float4
 
 // Dual step at one pixel of row s: y^{k+1} from y^k = (p, q) and xbar^k at
 // the pixel (ub, vb), its right neighbour (ub_r, vb_r; shifted by the caller)
-// and the row below (ub_d, vb_d).  ss scales the step of p; sq is the step of
-// q, ss / (2 alpha0), computed once per march by the caller.  The duals stay
-// as they are outside the mask.
+// and the row below (ub_d, vb_d).  sig is the step of p (base times the
+// iteration's factor); sq is the step of q, ss / (2 alpha0), computed once per
+// march by the caller.  The duals stay as they are outside the mask.
 template <bool TGV>
 __device__ inline void dual_step(float2 p, float4 q, float4 t, unsigned f, float ub, float2 vb, float ub_r,
-                                 float2 vb_r, float ub_d, float2 vb_d, float a0, float a1, float ss, float sq,
+                                 float2 vb_r, float ub_d, float2 vb_d, float a0, float a1, float sig, float sq,
                                  float2& pn, float4& qn)
 {
     pn = p;
@@ -251,11 +294,6 @@ __device__ inline void dual_step(float2 p, float4 q, float4 t, unsigned f, float
     const float pmx = (f & F_MX) ? 1.f : 0.f;
     const float pmy = (f & F_MY) ? 1.f : 0.f;
     const float gx = pmx * (ub_r - ub), gy = pmy * (ub_d - ub);
-    const float vrow = TGV ? a1 : 0.f;
-    const float s1 = a1 * (fabsf(t.x * pmx + t.y * pmy) + fabsf(t.x) * pmx + fabsf(t.y) * pmy) + vrow;
-    const float s2 = a1 * (fabsf(t.y * pmx + t.z * pmy) + fabsf(t.y) * pmx + fabsf(t.z) * pmy) + vrow;
-    const float smax = fmaxf(s1, s2);
-    const float sig = (smax > 0.f ? frcp(smax) : frcp(a1)) * ss;
     float p1 = p.x + sig * a1 * (t.x * gx + t.y * gy - (TGV ? vb.x : 0.f));
     float p2 = p.y + sig * a1 * (t.y * gx + t.z * gy - (TGV ? vb.y : 0.f));
     const float n2 = p1 * p1 + p2 * p2;
@@ -277,6 +315,24 @@ __device__ inline void dual_step(float2 p, float4 q, float4 t, unsigned f, float
         }
         qn = make_float4(q1, q2, q3, q4);
     }
+}
+
+// The steps above with the step sizes computed at the point of use: ts and ss
+// are the iteration's factors of the primal and dual steps.
+template <bool TGV>
+__device__ inline void primal_at(float u, float2 v, float2 p, float4 q, float4 t, float rho, unsigned f,
+                                 const Above& ab, float a0, float a1, float lambda, float ts, float& un, float2& vn)
+{
+    const PrimalBases b = primal_bases<TGV>(t, f, ab.cy, ab.my, a0, a1);
+    primal_step<TGV>(u, v, p, q, t, rho, f, ab, a0, a1, lambda, b.tu * ts, b.tv * ts, un, vn);
+}
+
+template <bool TGV>
+__device__ inline void dual_at(float2 p, float4 q, float4 t, unsigned f, float ub, float2 vb, float ub_r,
+                               float2 vb_r, float ub_d, float2 vb_d, float a0, float a1, float ss, float sq,
+                               float2& pn, float4& qn)
+{
+    dual_step<TGV>(p, q, t, f, ub, vb, ub_r, vb_r, ub_d, vb_d, a0, a1, dual_base<TGV>(t, f, a1) * ss, sq, pn, qn);
 }
 
 // XCD-aware renumbering of the workgroup index.
@@ -360,7 +416,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a, int by, i
         float un = c.u;
         float2 vn = c.v;
         if (PRIMAL) {
-            primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab, a0, a1, a.lambda, a.tau_scale, un, vn);
+            primal_at<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab, a0, a1, a.lambda, a.tau_scale, un, vn);
             if (owner && r < y1) {
                 const size_t o = (size_t)r * P.pitch + x;
                 P.u_out[o] = un;
@@ -377,8 +433,8 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a, int by, i
             if (r > y0 && owner) {
                 float2 pn;
                 float4 qn;
-                dual_step<TGV>(p_prev, q_prev, t_prev, f_prev, ub_prev, vb_prev, ub_r, vb_r, ub, vb, a0, a1,
-                               a.sigma_scale, sq1, pn, qn);
+                dual_at<TGV>(p_prev, q_prev, t_prev, f_prev, ub_prev, vb_prev, ub_r, vb_r, ub, vb, a0, a1,
+                             a.sigma_scale, sq1, pn, qn);
                 const size_t o = (size_t)(r - 1) * P.pitch + x;
                 st2<S>(P.p_out, o, pn);
                 if (TGV) st4<S>(P.q_out, o, qn);
@@ -463,7 +519,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
             } else {
                 c = load_row<TGV, true, S>(P, x, r, in_x);
             }
-            primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, a.tau_scale, un1, vn1);
+            primal_at<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, a.tau_scale, un1, vn1);
             ub1 = un1 + a.theta * (un1 - c.u);
             vb1 = make_float2(vn1.x + a.theta * (vn1.x - c.v.x), vn1.y + a.theta * (vn1.y - c.v.y));
         }
@@ -473,8 +529,8 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
         if (r >= y0 && r <= y1 + 1) {
             const float ub_r = from_right(ub1_m1);
             const float2 vb_r = make_float2(from_right(vb1_m1.x), from_right(vb1_m1.y));
-            dual_step<TGV>(p_m1, q_m1, t_m1, f_m1, ub1_m1, vb1_m1, ub_r, vb_r, ub1, vb1, a0, a1, a.sigma_scale,
-                           sq1, p1, q1);
+            dual_at<TGV>(p_m1, q_m1, t_m1, f_m1, ub1_m1, vb1_m1, ub_r, vb_r, ub1, vb1, a0, a1, a.sigma_scale,
+                         sq1, p1, q1);
         }
         // C: iteration-2 primal at row r-2 -> x^{k+1}(r-2)
         float ub2 = 0.f;
@@ -482,8 +538,8 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
         if (r >= y0 + 2) {
             float un2;
             float2 vn2;
-            primal_step<TGV>(un1_m2, vn1_m2, p1_m2, q1_m2, t_m2, rho_m2, f_m2, ab2, a0, a1, lam, a.tau_scale2,
-                             un2, vn2);
+            primal_at<TGV>(un1_m2, vn1_m2, p1_m2, q1_m2, t_m2, rho_m2, f_m2, ab2, a0, a1, lam, a.tau_scale2,
+                           un2, vn2);
             ub2 = un2 + a.theta2 * (un2 - un1_m2);
             vb2 = make_float2(vn2.x + a.theta2 * (vn2.x - vn1_m2.x), vn2.y + a.theta2 * (vn2.y - vn1_m2.y));
             if (owner && r - 2 < y1) {
@@ -498,8 +554,8 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
             const float2 vb_r = make_float2(from_right(vb2_m3.x), from_right(vb2_m3.y));
             float2 pn;
             float4 qn;
-            dual_step<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1, a.sigma_scale2,
-                           sq2, pn, qn);
+            dual_at<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1, a.sigma_scale2,
+                         sq2, pn, qn);
             if (owner) {
                 const size_t o = (size_t)(r - 3) * P.pitch + x;
                 st2<S>(P.p_out, o, pn);
@@ -569,6 +625,14 @@ template <> struct TensorRaw<ST_F32> {
     __device__ static float4 identity() { return make_float4(1.f, 0.f, 1.f, 0.f); }
 };
 
+// Whether a march computes each row's step-size bases once, when the row
+// enters, and carries them in a delay line beside the tensor, or at every use.
+// Both give the same values.  Carried where vector issue bounds the kernel and
+// the registers fit without losing a wavefront per SIMD: the 16-bit TGV
+// kernel of three iterations (124 VGPRs).  FP32 is co-limited by HBM and has
+// no room; the others would drop a wavefront.
+template <bool TGV, int S, int N> constexpr bool kCarryBases = TGV && S != ST_F32 && N == 3;
+
 // Downward march: at step r, iteration i takes its primal step at row r - 2i
 // and its dual step at row r - 2i - 1 (the dual needs xbar of the row below).
 template <bool TGV, int S, int N>
@@ -594,6 +658,13 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
         rhoD[d] = 0.f;
     }
     auto flag = [&](int d) { return unsigned(fD >> (8 * d)) & 0xffu; };
+    // carried step-size bases of rows r - d (primal of u and v, dual of p),
+    // and the step-size part of the row above the entering row
+    constexpr bool CB = kCarryBases<TGV, S, N>;
+    float tuD[D], tvD[D], sgD[D];
+    float cy_up = 0.f, my_up = 0.f;
+#pragma unroll
+    for (int d = 0; d < D; ++d) tuD[d] = tvD[d] = sgD[d] = 0.f;
     // per iteration i: its primal outputs x of the last two steps, its xbar
     // of the last step, its dual outputs y of the last two steps
     float xu[N][2], xbu[N];
@@ -620,6 +691,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
         q_m1 = w.q;
         tD[0] = TensorRaw<S>::pack(w.t);
         fD = w.f;
+        above_steps(w.t, w.f, cy_up, my_up);
     }
     const int r_lo = y0 - (N - 1), r_hi = y1 + 2 * N - 2, r_load = y1 + N - 1;
     // no prefetch here: its registers would cost a wavefront per SIMD, which
@@ -646,6 +718,19 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
         tD[0] = TensorRaw<S>::pack(c.t);
         rhoD[0] = c.rho;
         fD = (fD << 8) | c.f;
+        if constexpr (CB) {
+#pragma unroll
+            for (int d = D - 1; d > 0; --d) {
+                tuD[d] = tuD[d - 1];
+                tvD[d] = tvD[d - 1];
+                sgD[d] = sgD[d - 1];
+            }
+            const PrimalBases b = primal_bases<TGV>(c.t, c.f, cy_up, my_up, a0, a1);
+            tuD[0] = b.tu;
+            tvD[0] = b.tv;
+            sgD[0] = dual_base<TGV>(c.t, c.f, a1);
+            above_steps(c.t, c.f, cy_up, my_up);
+        }
 
         float xnu[N], xbnu[N];
         float2 xnv[N], xbnv[N], ynp[N];
@@ -669,8 +754,13 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             if (pr >= lo && pr <= hi) {
                 float un;
                 float2 vn;
-                primal_step<TGV>(u_in, v_in, p_in, q_in, i == 0 ? c.t : TensorRaw<S>::unpack(tD[2 * i]),
-                                 rhoD[2 * i], flag(2 * i), ab, a0, a1, lam, a.tau_n[i], un, vn);
+                const float4 t_q = i == 0 ? c.t : TensorRaw<S>::unpack(tD[2 * i]);
+                if constexpr (CB)
+                    primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[2 * i], flag(2 * i), ab, a0, a1, lam,
+                                     tuD[2 * i] * a.tau_n[i], tvD[2 * i] * a.tau_n[i], un, vn);
+                else
+                    primal_at<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[2 * i], flag(2 * i), ab, a0, a1, lam,
+                                   a.tau_n[i], un, vn);
                 const float th = a.theta_n[i];
                 xnu[i] = un;
                 xnv[i] = vn;
@@ -691,8 +781,12 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
                 const float4 qy = i == 0 ? q_m1 : yq[i - 1][1];
                 const float ub_r = from_right(xbu[i]);
                 const float2 vb_r = make_float2(from_right(xbv[i].x), from_right(xbv[i].y));
-                dual_step<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, xbnu[i], xbnv[i], a0, a1,
-                               a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
+                if constexpr (CB)
+                    dual_step<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, xbnu[i], xbnv[i], a0,
+                                   a1, sgD[2 * i + 1] * a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
+                else
+                    dual_at<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, xbnu[i], xbnv[i], a0, a1,
+                                 a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
                 if (i == N - 1 && owner && dr >= y0 && dr < y1) {
                     const size_t o = (size_t)dr * P.pitch + x;
                     st2<S>(P.p_out, o, ynp[i]);
@@ -744,6 +838,11 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
         rhoD[d] = 0.f;
     }
     auto flag = [&](int d) { return unsigned(fD >> (8 * d)) & 0xffu; };
+    // carried step-size bases of rows r + d (primal of u and v, dual of p)
+    constexpr bool CB = kCarryBases<TGV, S, N>;
+    float tuD[N], tvD[N], sgD[N];
+#pragma unroll
+    for (int d = 0; d < N; ++d) tuD[d] = tvD[d] = sgD[d] = 0.f;
     // per iteration i, from its previous step (row r + 1 + i): primal output,
     // xbar and dual output
     float xu[N], xbu[N];
@@ -771,6 +870,20 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
         tD[0] = TensorRaw<S>::pack(c.t);
         rhoD[0] = c.rho;
         fD = (fD << 8) | c.f;
+        if constexpr (CB) {
+#pragma unroll
+            for (int d = N - 1; d > 0; --d) {
+                tuD[d] = tuD[d - 1];
+                tvD[d] = tvD[d - 1];
+                sgD[d] = sgD[d - 1];
+            }
+            float cy_up, my_up;
+            above_steps(nx.t, nx.f, cy_up, my_up);
+            const PrimalBases b = primal_bases<TGV>(c.t, c.f, cy_up, my_up, a0, a1);
+            tuD[0] = b.tu;
+            tvD[0] = b.tv;
+            sgD[0] = dual_base<TGV>(c.t, c.f, a1);
+        }
 
         float xnu[N], xbnu[N];
         float2 xnv[N], xbnv[N], ynp[N];
@@ -793,7 +906,12 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
             if (q >= lo && q <= hi) {
                 float un;
                 float2 vn;
-                primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[i], flag(i), ab, a0, a1, lam, a.tau_n[i], un, vn);
+                if constexpr (CB)
+                    primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[i], flag(i), ab, a0, a1, lam,
+                                     tuD[i] * a.tau_n[i], tvD[i] * a.tau_n[i], un, vn);
+                else
+                    primal_at<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[i], flag(i), ab, a0, a1, lam, a.tau_n[i], un,
+                                   vn);
                 const float th = a.theta_n[i];
                 xnu[i] = un;
                 xnv[i] = vn;
@@ -810,8 +928,12 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
             if (q >= lo && q <= hi - 1) {
                 const float ub_r = from_right(xbnu[i]);
                 const float2 vb_r = make_float2(from_right(xbnv[i].x), from_right(xbnv[i].y));
-                dual_step<TGV>(p_in, q_in, t_q, flag(i), xbnu[i], xbnv[i], ub_r, vb_r, xbu[i], xbv[i], a0, a1,
-                               a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
+                if constexpr (CB)
+                    dual_step<TGV>(p_in, q_in, t_q, flag(i), xbnu[i], xbnv[i], ub_r, vb_r, xbu[i], xbv[i], a0, a1,
+                                   sgD[i] * a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
+                else
+                    dual_at<TGV>(p_in, q_in, t_q, flag(i), xbnu[i], xbnv[i], ub_r, vb_r, xbu[i], xbv[i], a0, a1,
+                                 a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
                 if (i == N - 1 && owner && q >= y0 && q < y1) {
                     const size_t o = (size_t)q * P.pitch + x;
                     st2<S>(P.p_out, o, ynp[i]);
