@@ -64,7 +64,8 @@ constexpr int kCols2 = kLanes - 4;   // owned columns per wavefront, PD_FUSED2
 // moment close together, measured faster than long ones at equal traffic).
 // With less: one round of marches as long as fit, but at least kBYs rows
 // (long marches re-read fewer halo rows, and no partly filled last round
-// idles the chip).
+// idles the chip); multi-iteration launches too small to fill the SIMDs may
+// go shorter (short_march_floor).
 constexpr int kBY = 16;
 constexpr int kBYs = 4;
 constexpr long long kRoundsForShort = 4;
@@ -1007,6 +1008,23 @@ long long resident_waves(K kernel)
     return w;
 }
 
+// SIMDs of the current device (compute units x 4), cached per device.
+long long device_simds()
+{
+    static std::mutex mu;
+    static std::map<int, long long> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    const long long n = 4LL * cus;
+    cache.emplace(dev, n);
+    return n;
+}
+
 // Segment height, segment count and workgroups of a launch whose wavefronts
 // own `cols` columns (blocks = 0: nothing to do).
 struct March {
@@ -1014,8 +1032,25 @@ struct March {
     long long blocks;
 };
 
+// The shortest march a multi-iteration launch may use.  Short marches cost
+// halo rows; they pay where the launch cannot fill the SIMDs anyway and its
+// time is one wavefront's chain of row steps: down to 1 row while the launch
+// holds at most one wavefront per SIMD, to 2 rows while it holds at most two
+// (measured on the 32x32 to 256x256 pyramid levels of 8 pairs: 16.4 -> 11.6,
+// 16.6 -> 11.8 and 17.1 -> 16.0 us per launch; shorter marches at 256x256
+// were slower).
+int short_march_floor(const PdArgs& a, int cols)
+{
+    const long long H = a.lc.g.H[a.lc.gl];
+    const long long strips = (long long)(a.lc.g.W[a.lc.gl] + cols - 1) / cols * a.lc.n;
+    const long long simds = device_simds();
+    if (strips * H <= simds) return 1;
+    if (strips * ((H + 1) / 2) <= 2 * simds) return 2;
+    return kBYs;
+}
+
 template <typename K>
-March march_shape(const PdArgs& a, int cols, K kernel)
+March march_shape(const PdArgs& a, int cols, K kernel, int min_by = kBYs)
 {
     March m{0, 0, 0};
     const int H = a.lc.g.H[a.lc.gl];
@@ -1032,7 +1067,7 @@ March march_shape(const PdArgs& a, int cols, K kernel)
     }
     if (segs < 1) segs = 1;
     int by = int((H + segs - 1) / segs);
-    if (by < kBYs) by = kBYs;
+    if (by < min_by) by = min_by;
     m.by = by;
     m.segs = (H + by - 1) / by;
     m.blocks = (strips * m.segs + kWaves - 1) / kWaves;
@@ -1058,7 +1093,8 @@ void launch_fused2(const PdArgs& a, hipStream_t s)
 template <bool TGV, int S, int N>
 void launch_fusedn(const PdArgs& a, hipStream_t s)
 {
-    const March m = march_shape(a, kLanes - 2 * N, pdn_kernel<TGV, S, N>);
+    const March m =
+        march_shape(a, kLanes - 2 * N, pdn_kernel<TGV, S, N>, short_march_floor(a, kLanes - 2 * N));
     if (m.blocks)
         hipLaunchKernelGGL((pdn_kernel<TGV, S, N>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
@@ -1089,6 +1125,7 @@ void prepare_typed()
 
 void prepare_pd()
 {
+    (void)device_simds();
     prepare_typed<true, ST_F32>();
     prepare_typed<true, ST_F16>();
     prepare_typed<true, ST_BF16>();
