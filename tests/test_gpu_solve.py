@@ -204,3 +204,29 @@ def test_largest_and_ragged_batches(vfs, cid, n, check):
     if n == 32:
         with pytest.raises(vfs.VfsError, match="n must be"):
             vfs.solve_batch(R, I0s + I0s[:1], I1s + I1s[:1], params)
+
+
+@pytest.mark.parametrize("storage", [0, 1], ids=["f32", "f16"])
+@pytest.mark.parametrize("reg", ["tgv", "tv"])
+def test_identical_or_textureless_pairs(vfs, reg, storage):
+    """Degenerate inputs on the unrotated 128x128 rig, in one batch: a pair of
+    identical images and a textureless pair.  The oracle's answer is exactly
+    zero displacement and no valid depth (its pin in test_oracle_solver); the
+    GPU's zero start, zero residuals and zero duals must stay zero through
+    every warp and level in both storage modes, and its validity must equal
+    the oracle's everywhere."""
+    import torch
+    d = inputs("c1")
+    rig, cfg = d["rig"], d["cfg"]
+    params = configs.solver_params(cfg, reg=reg, storage=storage)
+    I0 = d["I0"][0]
+    flat = np.full_like(I0, 0.4)
+    R = vfs.Rig(rig["cam0"], rig["cam1"], rig["R"], rig["t"], params["levels"])
+    outs = vfs.solve_batch(R, [_t(I0), _t(flat)], [_t(I0), _t(flat)], params)
+    torch.cuda.synchronize()
+    for A, o in zip((I0, flat), outs):
+        ref = oracle.solve(rig["cam0"], rig["cam1"], rig["R"], rig["t"], dict(params, storage=0),
+                           A.astype(np.float64), A.astype(np.float64))
+        assert not ref["u"].any() and not ref["valid"].any()
+        assert not _np(o["u"]).any() and not _np(o["w"]).any()
+        assert np.array_equal(_np(o["valid"]).astype(bool), ref["valid"].astype(bool))

@@ -324,3 +324,22 @@ def test_c2_room_outliers(c2_inputs):
     epe = np.linalg.norm(out["w"] - gt["flow"], axis=-1)[ev]
     frac = np.mean(epe > 1.0)
     assert frac <= 0.10, frac
+
+
+@pytest.mark.parametrize("reg", ["tgv", "tv"])
+def test_identical_or_textureless_pairs_give_zero_displacement(reg, c1_inputs):
+    """Degenerate inputs with a closed-form answer.  On the unrotated 128x128
+    rig (pre-rotation is the identity), a pair of identical images has zero
+    residual at zero displacement, and a textureless pair has no data term at
+    all; from the zero start the duals stay zero, so every warp of every
+    level keeps u = 0 (Eqs. (8)-(13)), w = 0, and with zero displacement the
+    two rays of a translating rig are parallel: no depth anywhere."""
+    d = c1_inputs
+    rig, cfg = d["rig"], d["cfg"]
+    assert np.array_equal(np.asarray(rig["R"]), np.eye(3))
+    params = configs.solver_params(cfg, reg=reg)
+    I0 = d["I0"][0].astype(np.float64)
+    for A, B in ((I0, I0), (np.full_like(I0, 0.4), np.full_like(I0, 0.4))):
+        o = oracle.solve(rig["cam0"], rig["cam1"], rig["R"], rig["t"], params, A, B)
+        assert not o["u"].any() and not o["w"].any()
+        assert not o["valid"].any()
