@@ -628,11 +628,12 @@ template <> struct TensorRaw<ST_F32> {
 
 // Whether a march computes each row's step-size bases once, when the row
 // enters, and carries them in a delay line beside the tensor, or at every use.
-// Both give the same values.  Carried where vector issue bounds the kernel and
-// the registers fit without losing a wavefront per SIMD: the 16-bit TGV
-// kernel of three iterations (124 VGPRs).  FP32 is co-limited by HBM and has
-// no room; the others would drop a wavefront.
+// Both give the same values.  Carried where the registers fit without losing
+// a wavefront per SIMD: all of them (primal of u and v, dual of p) in the
+// 16-bit TGV kernel of three iterations (124 VGPRs), the dual one only in the
+// FP32 one (123 VGPRs); the four-iteration kernels would drop a wavefront.
 template <bool TGV, int S, int N> constexpr bool kCarryBases = TGV && S != ST_F32 && N == 3;
+template <bool TGV, int S, int N> constexpr bool kCarryDual = TGV && N == 3;
 
 // Downward march: at step r, iteration i takes its primal step at row r - 2i
 // and its dual step at row r - 2i - 1 (the dual needs xbar of the row below).
@@ -659,9 +660,11 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
         rhoD[d] = 0.f;
     }
     auto flag = [&](int d) { return unsigned(fD >> (8 * d)) & 0xffu; };
-    // carried step-size bases of rows r - d (primal of u and v, dual of p),
-    // and the step-size part of the row above the entering row
+    // carried step-size bases of rows r - d (primal of u and v if CB, dual
+    // of p if CB or CD), and the step-size part of the row above the entering
+    // row
     constexpr bool CB = kCarryBases<TGV, S, N>;
+    constexpr bool CD = kCarryDual<TGV, S, N>;
     float tuD[D], tvD[D], sgD[D];
     float cy_up = 0.f, my_up = 0.f;
 #pragma unroll
@@ -724,13 +727,16 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             for (int d = D - 1; d > 0; --d) {
                 tuD[d] = tuD[d - 1];
                 tvD[d] = tvD[d - 1];
-                sgD[d] = sgD[d - 1];
             }
             const PrimalBases b = primal_bases<TGV>(c.t, c.f, cy_up, my_up, a0, a1);
             tuD[0] = b.tu;
             tvD[0] = b.tv;
-            sgD[0] = dual_base<TGV>(c.t, c.f, a1);
             above_steps(c.t, c.f, cy_up, my_up);
+        }
+        if constexpr (CB || CD) {
+#pragma unroll
+            for (int d = D - 1; d > 0; --d) sgD[d] = sgD[d - 1];
+            sgD[0] = dual_base<TGV>(c.t, c.f, a1);
         }
 
         float xnu[N], xbnu[N];
@@ -782,7 +788,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
                 const float4 qy = i == 0 ? q_m1 : yq[i - 1][1];
                 const float ub_r = from_right(xbu[i]);
                 const float2 vb_r = make_float2(from_right(xbv[i].x), from_right(xbv[i].y));
-                if constexpr (CB)
+                if constexpr (CB || CD)
                     dual_step<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, xbnu[i], xbnv[i], a0,
                                    a1, sgD[2 * i + 1] * a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
                 else
@@ -839,8 +845,10 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
         rhoD[d] = 0.f;
     }
     auto flag = [&](int d) { return unsigned(fD >> (8 * d)) & 0xffu; };
-    // carried step-size bases of rows r + d (primal of u and v, dual of p)
+    // carried step-size bases of rows r + d (primal of u and v if CB, dual
+    // of p if CB or CD)
     constexpr bool CB = kCarryBases<TGV, S, N>;
+    constexpr bool CD = kCarryDual<TGV, S, N>;
     float tuD[N], tvD[N], sgD[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) tuD[d] = tvD[d] = sgD[d] = 0.f;
@@ -876,13 +884,16 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
             for (int d = N - 1; d > 0; --d) {
                 tuD[d] = tuD[d - 1];
                 tvD[d] = tvD[d - 1];
-                sgD[d] = sgD[d - 1];
             }
             float cy_up, my_up;
             above_steps(nx.t, nx.f, cy_up, my_up);
             const PrimalBases b = primal_bases<TGV>(c.t, c.f, cy_up, my_up, a0, a1);
             tuD[0] = b.tu;
             tvD[0] = b.tv;
+        }
+        if constexpr (CB || CD) {
+#pragma unroll
+            for (int d = N - 1; d > 0; --d) sgD[d] = sgD[d - 1];
             sgD[0] = dual_base<TGV>(c.t, c.f, a1);
         }
 
@@ -929,7 +940,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
             if (q >= lo && q <= hi - 1) {
                 const float ub_r = from_right(xbnu[i]);
                 const float2 vb_r = make_float2(from_right(xbnv[i].x), from_right(xbnv[i].y));
-                if constexpr (CB)
+                if constexpr (CB || CD)
                     dual_step<TGV>(p_in, q_in, t_q, flag(i), xbnu[i], xbnv[i], ub_r, vb_r, xbu[i], xbv[i], a0, a1,
                                    sgD[i] * a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
                 else
