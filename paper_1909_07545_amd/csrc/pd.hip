@@ -170,6 +170,15 @@ __device__ inline Row load_row(const Planes& P, int x, int r, bool in_x)
     return w;
 }
 
+// A flag bit as the float 0 or 1 that multiplies a masked difference: a
+// bit-field extract and one conversion.
+template <unsigned B>
+__device__ inline float flag_bit(unsigned f)
+{
+    static_assert(B && !(B & (B - 1)), "one flag bit");
+    return float((f >> __builtin_ctz(B)) & 1u);
+}
+
 // What the primal step of row r reads from row r - 1 (the y-parts of the
 // masked divergences and of the column sums of the preconditioner).
 struct Above {
@@ -180,7 +189,7 @@ struct Above {
 // depend on the tensor and the mask bits only).
 __device__ inline void above_steps(float4 t, unsigned f, float& cy, float& my)
 {
-    my = (f & F_MY) ? 1.f : 0.f;
+    my = flag_bit<F_MY>(f);
     cy = my * (fabsf(t.y) + fabsf(t.z));
 }
 
@@ -220,8 +229,8 @@ struct PrimalBases {
 template <bool TGV>
 __device__ inline PrimalBases primal_bases(float4 t, unsigned f, float cy_up, float my_up, float a0, float a1)
 {
-    const float mx = (f & F_MX) ? 1.f : 0.f;
-    const float my = (f & F_MY) ? 1.f : 0.f;
+    const float mx = flag_bit<F_MX>(f);
+    const float my = flag_bit<F_MY>(f);
     const float cx = mx * (fabsf(t.x) + fabsf(t.y));
     const float cx_l = from_left(cx);
     const float cu = fabsf(t.x * mx + t.y * my) + fabsf(t.y * mx + t.z * my) + cx_l + cy_up;
@@ -239,8 +248,8 @@ __device__ inline PrimalBases primal_bases(float4 t, unsigned f, float cy_up, fl
 template <bool TGV>
 __device__ inline float dual_base(float4 t, unsigned f, float a1)
 {
-    const float pmx = (f & F_MX) ? 1.f : 0.f;
-    const float pmy = (f & F_MY) ? 1.f : 0.f;
+    const float pmx = flag_bit<F_MX>(f);
+    const float pmy = flag_bit<F_MY>(f);
     const float vrow = TGV ? a1 : 0.f;
     const float s1 = a1 * (fabsf(t.x * pmx + t.y * pmy) + fabsf(t.x) * pmx + fabsf(t.y) * pmy) + vrow;
     const float s2 = a1 * (fabsf(t.y * pmx + t.z * pmy) + fabsf(t.y) * pmx + fabsf(t.z) * pmy) + vrow;
@@ -258,8 +267,8 @@ __device__ inline void primal_step(float u, float2 v, float2 p, float4 q, float4
                                    const Above& ab, float a0, float a1, float lambda, float tau_u, float tau_v,
                                    float& un, float2& vn)
 {
-    const float mx = (f & F_MX) ? 1.f : 0.f;
-    const float my = (f & F_MY) ? 1.f : 0.f;
+    const float mx = flag_bit<F_MX>(f);
+    const float my = flag_bit<F_MY>(f);
     const float ax = mx * (t.x * p.x + t.y * p.y);
     const float ax_l = from_left(ax);
     const float b = my * (t.y * p.x + t.z * p.y);
@@ -292,8 +301,8 @@ __device__ inline void dual_step(float2 p, float4 q, float4 t, unsigned f, float
     pn = p;
     qn = q;
     if (!(f & F_MASK)) return;
-    const float pmx = (f & F_MX) ? 1.f : 0.f;
-    const float pmy = (f & F_MY) ? 1.f : 0.f;
+    const float pmx = flag_bit<F_MX>(f);
+    const float pmy = flag_bit<F_MY>(f);
     const float gx = pmx * (ub_r - ub), gy = pmy * (ub_d - ub);
     float p1 = p.x + sig * a1 * (t.x * gx + t.y * gy - (TGV ? vb.x : 0.f));
     float p2 = p.y + sig * a1 * (t.y * gx + t.z * gy - (TGV ? vb.y : 0.f));
