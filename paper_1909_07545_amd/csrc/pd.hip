@@ -638,11 +638,9 @@ template <> struct TensorRaw<ST_F32> {
 // Whether a march computes each row's step-size bases once, when the row
 // enters, and carries them in a delay line beside the tensor, or at every use.
 // Both give the same values.  Carried where the registers fit without losing
-// a wavefront per SIMD: all of them (primal of u and v, dual of p) in the
-// 16-bit TGV kernel of three iterations (124 VGPRs), the dual one only in the
-// FP32 one (123 VGPRs); the four-iteration kernels would drop a wavefront.
-template <bool TGV, int S, int N> constexpr bool kCarryBases = TGV && S != ST_F32 && N == 3;
-template <bool TGV, int S, int N> constexpr bool kCarryDual = TGV && N == 3;
+// a wavefront per SIMD: the TGV kernels of three iterations (FP32 125 VGPRs,
+// 16-bit 118); the four-iteration kernels would drop one.
+template <bool TGV, int S, int N> constexpr bool kCarryBases = TGV && N == 3;
 
 // Downward march: at step r, iteration i takes its primal step at row r - 2i
 // and its dual step at row r - 2i - 1 (the dual needs xbar of the row below).
@@ -669,11 +667,9 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
         rhoD[d] = 0.f;
     }
     auto flag = [&](int d) { return unsigned(fD >> (8 * d)) & 0xffu; };
-    // carried step-size bases of rows r - d (primal of u and v if CB, dual
-    // of p if CB or CD), and the step-size part of the row above the entering
-    // row
+    // carried step-size bases of rows r - d (primal of u and v, dual of p),
+    // and the step-size part of the row above the entering row
     constexpr bool CB = kCarryBases<TGV, S, N>;
-    constexpr bool CD = kCarryDual<TGV, S, N>;
     float tuD[D], tvD[D], sgD[D];
     float cy_up = 0.f, my_up = 0.f;
 #pragma unroll
@@ -736,26 +732,28 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             for (int d = D - 1; d > 0; --d) {
                 tuD[d] = tuD[d - 1];
                 tvD[d] = tvD[d - 1];
+                sgD[d] = sgD[d - 1];
             }
             const PrimalBases b = primal_bases<TGV>(c.t, c.f, cy_up, my_up, a0, a1);
             tuD[0] = b.tu;
             tvD[0] = b.tv;
+            sgD[0] = dual_base<TGV>(c.t, c.f, a1);
             above_steps(c.t, c.f, cy_up, my_up);
         }
-        if constexpr (CB || CD) {
-#pragma unroll
-            for (int d = D - 1; d > 0; --d) sgD[d] = sgD[d - 1];
-            sgD[0] = dual_base<TGV>(c.t, c.f, a1);
-        }
 
-        float xnu[N], xbnu[N];
-        float2 xnv[N], xbnv[N], ynp[N];
-        float4 ynq[N];
+        // Later iterations first: iteration i reads iteration i - 1's
+        // windows as they stood after the previous step.  An iteration
+        // updates its windows only at steps inside its rows; it is inside
+        // them at the two steps before any step at which iteration i + 1
+        // (or its own dual) reads them, so every read sees the same values
+        // as with a shift at every step.
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
+        for (int k = 0; k < N; ++k) {
+            const int i = N - 1 - k;
             const int lo = y0 - (N - 1 - i), hi = y1 + (N - 1 - i);
             // primal step of iteration i at row r - 2i
             const int pr = r - 2 * i;
+            if (pr < lo || pr > hi) continue;
             const float u_in = i == 0 ? c.u : xu[i - 1][1];
             const float2 v_in = i == 0 ? c.v : xv[i - 1][1];
             const float2 p_in = i == 0 ? c.p : yp[i - 1][0];
@@ -763,66 +761,55 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             const float4 t_ab = TensorRaw<S>::unpack(tD[2 * i + 1]);
             const Above ab = i == 0 ? above_of(p_m1, q_m1, t_ab, flag(1))
                                     : above_of(yp[i - 1][1], yq[i - 1][1], t_ab, flag(2 * i + 1));
-            xnu[i] = 0.f;
-            xnv[i] = make_float2(0.f, 0.f);
-            xbnu[i] = 0.f;
-            xbnv[i] = make_float2(0.f, 0.f);
-            if (pr >= lo && pr <= hi) {
-                float un;
-                float2 vn;
-                const float4 t_q = i == 0 ? c.t : TensorRaw<S>::unpack(tD[2 * i]);
-                if constexpr (CB)
-                    primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[2 * i], flag(2 * i), ab, a0, a1, lam,
-                                     tuD[2 * i] * a.tau_n[i], tvD[2 * i] * a.tau_n[i], un, vn);
-                else
-                    primal_at<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[2 * i], flag(2 * i), ab, a0, a1, lam,
-                                   a.tau_n[i], un, vn);
-                const float th = a.theta_n[i];
-                xnu[i] = un;
-                xnv[i] = vn;
-                xbnu[i] = un + th * (un - u_in);
-                xbnv[i] = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
-                if (i == N - 1 && owner && pr >= y0 && pr < y1) {
-                    const size_t o = (size_t)pr * P.pitch + x;
-                    P.u_out[o] = un;
-                    if (TGV) P.v_out[o] = vn;
-                }
+            float un;
+            float2 vn;
+            const float4 t_q = i == 0 ? c.t : TensorRaw<S>::unpack(tD[2 * i]);
+            if constexpr (CB)
+                primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[2 * i], flag(2 * i), ab, a0, a1, lam,
+                                 tuD[2 * i] * a.tau_n[i], tvD[2 * i] * a.tau_n[i], un, vn);
+            else
+                primal_at<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[2 * i], flag(2 * i), ab, a0, a1, lam, a.tau_n[i],
+                               un, vn);
+            const float th = a.theta_n[i];
+            const float ubn = un + th * (un - u_in);
+            const float2 vbn = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
+            if (i == N - 1 && owner && pr >= y0 && pr < y1) {
+                const size_t o = (size_t)pr * P.pitch + x;
+                P.u_out[o] = un;
+                if (TGV) P.v_out[o] = vn;
             }
-            // dual step of iteration i at row r - 2i - 1
+            // dual step of iteration i at row r - 2i - 1 (inside its rows
+            // whenever the row below is, save the first)
             const int dr = pr - 1;
-            ynp[i] = make_float2(0.f, 0.f);
-            ynq[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (dr >= lo && dr <= hi - 1) {
+            if (dr >= lo) {
                 const float2 py = i == 0 ? p_m1 : yp[i - 1][1];
                 const float4 qy = i == 0 ? q_m1 : yq[i - 1][1];
                 const float ub_r = from_right(xbu[i]);
                 const float2 vb_r = make_float2(from_right(xbv[i].x), from_right(xbv[i].y));
-                if constexpr (CB || CD)
-                    dual_step<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, xbnu[i], xbnv[i], a0,
-                                   a1, sgD[2 * i + 1] * a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
+                float2 pn;
+                float4 qn;
+                if constexpr (CB)
+                    dual_step<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, ubn, vbn, a0, a1,
+                                   sgD[2 * i + 1] * a.sigma_n[i], sqn[i], pn, qn);
                 else
-                    dual_at<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, xbnu[i], xbnv[i], a0, a1,
-                                 a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
+                    dual_at<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, ubn, vbn, a0, a1,
+                                 a.sigma_n[i], sqn[i], pn, qn);
                 if (i == N - 1 && owner && dr >= y0 && dr < y1) {
                     const size_t o = (size_t)dr * P.pitch + x;
-                    st2<S>(P.p_out, o, ynp[i]);
-                    if (TGV) st4<S>(P.q_out, o, ynq[i]);
+                    st2<S>(P.p_out, o, pn);
+                    if (TGV) st4<S>(P.q_out, o, qn);
                 }
+                yp[i][1] = yp[i][0];
+                yp[i][0] = pn;
+                yq[i][1] = yq[i][0];
+                yq[i][0] = qn;
             }
-        }
-        // slide the windows
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
             xu[i][1] = xu[i][0];
-            xu[i][0] = xnu[i];
+            xu[i][0] = un;
             xv[i][1] = xv[i][0];
-            xv[i][0] = xnv[i];
-            xbu[i] = xbnu[i];
-            xbv[i] = xbnv[i];
-            yp[i][1] = yp[i][0];
-            yp[i][0] = ynp[i];
-            yq[i][1] = yq[i][0];
-            yq[i][0] = ynq[i];
+            xv[i][0] = vn;
+            xbu[i] = ubn;
+            xbv[i] = vbn;
         }
         p_m1 = c.p;
         q_m1 = c.q;
@@ -854,10 +841,8 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
         rhoD[d] = 0.f;
     }
     auto flag = [&](int d) { return unsigned(fD >> (8 * d)) & 0xffu; };
-    // carried step-size bases of rows r + d (primal of u and v if CB, dual
-    // of p if CB or CD)
+    // carried step-size bases of rows r + d (primal of u and v, dual of p)
     constexpr bool CB = kCarryBases<TGV, S, N>;
-    constexpr bool CD = kCarryDual<TGV, S, N>;
     float tuD[N], tvD[N], sgD[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) tuD[d] = tvD[d] = sgD[d] = 0.f;
@@ -893,16 +878,13 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
             for (int d = N - 1; d > 0; --d) {
                 tuD[d] = tuD[d - 1];
                 tvD[d] = tvD[d - 1];
+                sgD[d] = sgD[d - 1];
             }
             float cy_up, my_up;
             above_steps(nx.t, nx.f, cy_up, my_up);
             const PrimalBases b = primal_bases<TGV>(c.t, c.f, cy_up, my_up, a0, a1);
             tuD[0] = b.tu;
             tvD[0] = b.tv;
-        }
-        if constexpr (CB || CD) {
-#pragma unroll
-            for (int d = N - 1; d > 0; --d) sgD[d] = sgD[d - 1];
             sgD[0] = dual_base<TGV>(c.t, c.f, a1);
         }
 
@@ -949,7 +931,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
             if (q >= lo && q <= hi - 1) {
                 const float ub_r = from_right(xbnu[i]);
                 const float2 vb_r = make_float2(from_right(xbnv[i].x), from_right(xbnv[i].y));
-                if constexpr (CB || CD)
+                if constexpr (CB)
                     dual_step<TGV>(p_in, q_in, t_q, flag(i), xbnu[i], xbnv[i], ub_r, vb_r, xbu[i], xbv[i], a0, a1,
                                    sgD[i] * a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
                 else
