@@ -67,6 +67,11 @@ constexpr int kCols2 = kLanes - 4;   // owned columns per wavefront, PD_FUSED2
 // idles the chip); multi-iteration launches too small to fill the SIMDs may
 // go shorter (short_march_floor).
 constexpr int kBY = 16;
+// The 16-bit three-iteration kernel is bound by vector issue rather than by
+// memory: its marches aim at 28 rows, which re-compute fewer halo rows
+// (measured on 8 pairs of 2048x2048: 552 us per launch at 16 rows, 517 at
+// 28, 520 at 36; FP32 is slower beyond 16: 677, 685 at 22, 693 at 28).
+constexpr int kBY16 = 28;
 constexpr int kBYs = 4;
 constexpr long long kRoundsForShort = 4;
 constexpr int kXcds = 8;
@@ -1052,14 +1057,14 @@ int short_march_floor(const PdArgs& a, int cols)
 }
 
 template <typename K>
-March march_shape(const PdArgs& a, int cols, K kernel, int min_by = kBYs)
+March march_shape(const PdArgs& a, int cols, K kernel, int min_by = kBYs, int target_by = kBY)
 {
     March m{0, 0, 0};
     const int H = a.lc.g.H[a.lc.gl];
     const long long strips = (long long)(a.lc.g.W[a.lc.gl] + cols - 1) / cols * a.lc.n;
     if (strips < 1 || H < 1) return m;
     const long long slots = resident_waves(kernel);
-    const long long full = strips * ((H + kBY - 1) / kBY);
+    const long long full = strips * ((H + target_by - 1) / target_by);
     long long segs;
     if (full >= kRoundsForShort * slots) {
         const long long rounds = (full + slots / 2) / slots;
@@ -1095,8 +1100,8 @@ void launch_fused2(const PdArgs& a, hipStream_t s)
 template <bool TGV, int S, int N>
 void launch_fusedn(const PdArgs& a, hipStream_t s)
 {
-    const March m =
-        march_shape(a, kLanes - 2 * N, pdn_kernel<TGV, S, N>, short_march_floor(a, kLanes - 2 * N));
+    const March m = march_shape(a, kLanes - 2 * N, pdn_kernel<TGV, S, N>, short_march_floor(a, kLanes - 2 * N),
+                                S == ST_F32 ? kBY : kBY16);
     if (m.blocks)
         hipLaunchKernelGGL((pdn_kernel<TGV, S, N>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
