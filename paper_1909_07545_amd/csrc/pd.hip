@@ -64,8 +64,8 @@ constexpr int kCols2 = kLanes - 4;   // owned columns per wavefront, PD_FUSED2
 // moment close together, measured faster than long ones at equal traffic).
 // With less: one round of marches as long as fit, but at least kBYs rows
 // (long marches re-read fewer halo rows, and no partly filled last round
-// idles the chip); multi-iteration launches too small to fill the SIMDs may
-// go shorter (short_march_floor).
+// idles the chip); launches too small to fill the SIMDs go shorter
+// (short_march_floor).
 constexpr int kBY = 16;
 // The 16-bit three-iteration kernel is bound by vector issue rather than by
 // memory: its marches aim at 28 rows, which re-compute fewer halo rows
@@ -1039,13 +1039,14 @@ struct March {
     long long blocks;
 };
 
-// The shortest march a multi-iteration launch may use.  Short marches cost
-// halo rows; they pay where the launch cannot fill the SIMDs anyway and its
-// time is one wavefront's chain of row steps: down to 1 row while the launch
-// holds at most one wavefront per SIMD, to 2 rows while it holds at most two
+// The shortest march a launch may use.  Short marches cost halo rows; they
+// pay where the launch cannot fill the SIMDs anyway and its time is one
+// wavefront's chain of row steps: down to 1 row while the launch holds at
+// most one wavefront per SIMD, to 2 rows while it holds at most two
 // (measured on the 32x32 to 256x256 pyramid levels of 8 pairs: 16.4 -> 11.6,
-// 16.6 -> 11.8 and 17.1 -> 16.0 us per launch; shorter marches at 256x256
-// were slower).
+// 16.6 -> 11.8 and 17.1 -> 16.0 us per three-iteration launch; shorter
+// marches at 256x256 were slower; single-pair solves of 320x240 to 1024x768
+// pairs one at a time: 73 -> 94 pairs/s).
 int short_march_floor(const PdArgs& a, int cols)
 {
     const long long H = a.lc.g.H[a.lc.gl];
@@ -1084,7 +1085,7 @@ March march_shape(const PdArgs& a, int cols, K kernel, int min_by = kBYs, int ta
 template <int MODE, bool TGV, int S>
 void launch_mode(const PdArgs& a, hipStream_t s)
 {
-    const March m = march_shape(a, kCols, pd_kernel<MODE, TGV, S>);
+    const March m = march_shape(a, kCols, pd_kernel<MODE, TGV, S>, short_march_floor(a, kCols));
     if (m.blocks)
         hipLaunchKernelGGL((pd_kernel<MODE, TGV, S>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
@@ -1092,7 +1093,7 @@ void launch_mode(const PdArgs& a, hipStream_t s)
 template <bool TGV, int S>
 void launch_fused2(const PdArgs& a, hipStream_t s)
 {
-    const March m = march_shape(a, kCols2, pd2_kernel<TGV, S>);
+    const March m = march_shape(a, kCols2, pd2_kernel<TGV, S>, short_march_floor(a, kCols2));
     if (m.blocks)
         hipLaunchKernelGGL((pd2_kernel<TGV, S>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
