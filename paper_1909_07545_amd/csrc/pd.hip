@@ -517,6 +517,11 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
     Above ab2 = {0.f, 0.f, 0.f, 0.f, 0.f};
     float ub2_m3 = 0.f;
     float2 vb2_m3 = make_float2(0.f, 0.f);
+    // TGV: each row's step-size bases, computed once when A reaches the row
+    // and carried to C (primal, two steps later) and to B and D (dual, one
+    // and three steps later); the row above contributes its tensor and mask
+    // bits only, which A and C see alike
+    float tu_m1 = 0.f, tu_m2 = 0.f, tv_m1 = 0.f, tv_m2 = 0.f, sg_m1 = 0.f, sg_m2 = 0.f, sg_m3 = 0.f;
 
     // rows are loaded one step ahead of their use (see pd_kernel)
     constexpr bool PF = true;
@@ -525,7 +530,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
     for (int r = y0 - 1; r <= y1 + 2; ++r) {
         // A: iteration-1 primal at row r
         Row c = zero_row();
-        float un1 = 0.f, ub1 = 0.f;
+        float un1 = 0.f, ub1 = 0.f, tu0 = 0.f, tv0 = 0.f, sg0 = 0.f;
         float2 vn1 = make_float2(0.f, 0.f), vb1 = make_float2(0.f, 0.f);
         if (r <= y1 + 1) {
             if constexpr (PF) {
@@ -534,7 +539,16 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
             } else {
                 c = load_row<TGV, true, S>(P, x, r, in_x);
             }
-            primal_at<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, a.tau_scale, un1, vn1);
+            if constexpr (TGV) {
+                const PrimalBases b = primal_bases<TGV>(c.t, c.f, ab1.cy, ab1.my, a0, a1);
+                tu0 = b.tu;
+                tv0 = b.tv;
+                sg0 = dual_base<TGV>(c.t, c.f, a1);
+                primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, tu0 * a.tau_scale,
+                                 tv0 * a.tau_scale, un1, vn1);
+            } else {
+                primal_at<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, a.tau_scale, un1, vn1);
+            }
             ub1 = un1 + a.theta * (un1 - c.u);
             vb1 = make_float2(vn1.x + a.theta * (vn1.x - c.v.x), vn1.y + a.theta * (vn1.y - c.v.y));
         }
@@ -544,8 +558,12 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
         if (r >= y0 && r <= y1 + 1) {
             const float ub_r = from_right(ub1_m1);
             const float2 vb_r = make_float2(from_right(vb1_m1.x), from_right(vb1_m1.y));
-            dual_at<TGV>(p_m1, q_m1, t_m1, f_m1, ub1_m1, vb1_m1, ub_r, vb_r, ub1, vb1, a0, a1, a.sigma_scale,
-                         sq1, p1, q1);
+            if constexpr (TGV)
+                dual_step<TGV>(p_m1, q_m1, t_m1, f_m1, ub1_m1, vb1_m1, ub_r, vb_r, ub1, vb1, a0, a1,
+                               sg_m1 * a.sigma_scale, sq1, p1, q1);
+            else
+                dual_at<TGV>(p_m1, q_m1, t_m1, f_m1, ub1_m1, vb1_m1, ub_r, vb_r, ub1, vb1, a0, a1, a.sigma_scale,
+                             sq1, p1, q1);
         }
         // C: iteration-2 primal at row r-2 -> x^{k+1}(r-2)
         float ub2 = 0.f;
@@ -553,8 +571,12 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
         if (r >= y0 + 2) {
             float un2;
             float2 vn2;
-            primal_at<TGV>(un1_m2, vn1_m2, p1_m2, q1_m2, t_m2, rho_m2, f_m2, ab2, a0, a1, lam, a.tau_scale2,
-                           un2, vn2);
+            if constexpr (TGV)
+                primal_step<TGV>(un1_m2, vn1_m2, p1_m2, q1_m2, t_m2, rho_m2, f_m2, ab2, a0, a1, lam,
+                                 tu_m2 * a.tau_scale2, tv_m2 * a.tau_scale2, un2, vn2);
+            else
+                primal_at<TGV>(un1_m2, vn1_m2, p1_m2, q1_m2, t_m2, rho_m2, f_m2, ab2, a0, a1, lam, a.tau_scale2,
+                               un2, vn2);
             ub2 = un2 + a.theta2 * (un2 - un1_m2);
             vb2 = make_float2(vn2.x + a.theta2 * (vn2.x - vn1_m2.x), vn2.y + a.theta2 * (vn2.y - vn1_m2.y));
             if (owner && r - 2 < y1) {
@@ -569,8 +591,12 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
             const float2 vb_r = make_float2(from_right(vb2_m3.x), from_right(vb2_m3.y));
             float2 pn;
             float4 qn;
-            dual_at<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1, a.sigma_scale2,
-                         sq2, pn, qn);
+            if constexpr (TGV)
+                dual_step<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1,
+                               sg_m3 * a.sigma_scale2, sq2, pn, qn);
+            else
+                dual_at<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1,
+                             a.sigma_scale2, sq2, pn, qn);
             if (owner) {
                 const size_t o = (size_t)(r - 3) * P.pitch + x;
                 st2<S>(P.p_out, o, pn);
@@ -578,6 +604,13 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
             }
         }
         // slide the windows (deepest first)
+        tu_m2 = tu_m1;
+        tu_m1 = tu0;
+        tv_m2 = tv_m1;
+        tv_m1 = tv0;
+        sg_m3 = sg_m2;
+        sg_m2 = sg_m1;
+        sg_m1 = sg0;
         ab2 = above_of(p1_m2, q1_m2, t_m2, f_m2);      // row r-2, for C at row r-1
         t_m3 = t_m2;
         f_m3 = f_m2;
