@@ -34,6 +34,10 @@ oracle itself; the tests named live in ``tests/``):
 * ``threshold`` -- dense 1-D argmin of the prox objective (test_oracle_operators).
 * ``tensor`` -- eigen-structure {exp(-beta |g|^eta), 1} with eigenvector n,
   identity on constant images (test_oracle_operators).
+* ``energy`` -- equals Eq. (10) linearised, written out in the test with
+  the sparse gradient of its definition and the tensor entries applied by
+  hand, on random masked states with every term non-zero, TGV and TV
+  (test_oracle_operators).
 * ``pd_iterations`` -- converged iterates satisfy the optimality conditions
   of the linearised energy (subdifferential of Eq. (10), written from the
   energy, not from the iteration); energy decreases over each inner loop

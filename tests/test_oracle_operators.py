@@ -190,3 +190,52 @@ def test_steps_are_reciprocal_abs_sums_of_K(reg):
         assert np.allclose(tv.reshape(-1), 1.0 / col[2 * n:], rtol=1e-14, atol=0)
         # every q row has abs-sum 2 a0 or 0: sigma_q = 1/(2 a0) is the smallest safe value
         assert np.max(row[2 * n:]) == 2 * a0
+
+
+@pytest.mark.parametrize("reg", ["tgv", "tv"])
+@pytest.mark.parametrize("seed", range(3))
+def test_energy_is_eq10_written_with_explicit_operators(reg, seed):
+    """The linearised energy of Eq. (10) written out here with the sparse
+    gradient of the definition (entry by entry, not through the oracle):
+    E = sum over the mask of lambda |rho_c + u I_u| + alpha1 |(T grad u - v)_P|_2
+        + alpha0 |(grad v)_P|_F      (TV: v = 0, no last term),
+    on random masked states with v, I_u and rho_c non-zero everywhere, so a
+    dropped term, a sign, a swapped tensor entry or a missed mask changes the
+    value."""
+    rng = np.random.default_rng(20 + seed)
+    H, W = 17, 13
+    m = _random_mask(rng, H, W, 0.75)
+    n = H * W
+    J = rng.random((H, W))
+    T = oracle.tensor(J, m, 9.0, 0.85)
+    # perturb the tensor off its structured form so t11, t12, t22 are all
+    # distinct and a swapped entry shows
+    T = T + 0.1 * rng.normal(size=T.shape)
+    u = rng.normal(size=(H, W))
+    v = rng.normal(size=(H, W, 2)) if reg == "tgv" else None
+    Iu = rng.normal(0, 0.3, (H, W))
+    rho = rng.normal(0, 0.3, (H, W))
+    params = dict(levels=1, warps=1, iters=1, reg=reg, alpha0=17.0, alpha1=1.2, beta=9.0, eta=0.85,
+                  du_max=0.2, **{"lambda": 50.0})
+    G = _grad_matrix(m).tocsr()
+    Gx, Gy = G[0::2], G[1::2]
+    ux, uy = Gx @ u.reshape(-1), Gy @ u.reshape(-1)
+    t11, t12, t22 = (T[..., k].reshape(-1) for k in range(3))
+    a1 = t11 * ux + t12 * uy
+    a2 = t12 * ux + t22 * uy
+    if reg == "tgv":
+        a1 = a1 - v[..., 0].reshape(-1)
+        a2 = a2 - v[..., 1].reshape(-1)
+    inside = m.reshape(-1).astype(bool)
+    E = np.sum((50.0 * np.abs(rho.reshape(-1) + u.reshape(-1) * Iu.reshape(-1)))[inside])
+    E += np.sum((1.2 * np.hypot(a1, a2))[inside])
+    if reg == "tgv":
+        comps = [Gx @ v[..., 0].reshape(-1), Gy @ v[..., 0].reshape(-1),
+                 Gx @ v[..., 1].reshape(-1), Gy @ v[..., 1].reshape(-1)]
+        E += np.sum((17.0 * np.sqrt(sum(c * c for c in comps)))[inside])
+    Eo = oracle.energy(params, T, m, Iu, rho, u, v)
+    assert abs(Eo - E) <= 1e-12 * abs(E)
+    # each term is large enough on these states that dropping it would show
+    assert np.sum((1.2 * np.hypot(a1, a2))[inside]) > 1e-3 * E
+    if reg == "tgv":
+        assert np.sum((17.0 * np.sqrt(sum(c * c for c in comps)))[inside]) > 1e-3 * E
