@@ -169,8 +169,55 @@ vfs_status vfs_solve(vfs_rig* rig, const float* I0, const float* I1, size_t pitc
                      float* w_out, float* depth_out, float* z_out, uint8_t* valid_out,
                      const vfs_params* params, void* hip_stream);
 
+/* ---- Test hook: the state of a whole solve part-way through, for checking
+ * one warp of Algorithm 1 (the linearisation of Eqs. (3), (5); the
+ * iterations of Eq. (11) with the resolvent of Eq. (13); the clip and
+ * accumulation of Sec. III-C) against a reference started from exactly this
+ * state.
+ *
+ * vfs_solve_probe enqueues the launches of vfs_solve_batch on the same n
+ * pairs (same kernels, grids and batch) up to the end of warp `warp`
+ * (0 <= warp < params->warps) of pyramid level `level` (0 <= level <
+ * params->levels), copies pair `pair`'s state at three points of that warp,
+ * and stops there: no later warp or level, no triangulation, no outputs.
+ * Every destination is device memory with rows of `pitch` pixels (row bytes
+ * = pitch x the plane's bytes per pixel); NULL skips a plane.  Planes are
+ * level-l sized, H_l x W_l with W_l = W >> level, H_l = H >> level:
+ *   after the warp's linearisation, before its iterations:
+ *     J0, J1    float32: the level's pyramid images (J1 pre-rotated),
+ *     u         float32: u after the previous warp's clip (= u_w),
+ *     w         float32 pairs: warping vectors after that clip,
+ *     v         float32 pairs (TGV): the warm-started primal v,
+ *     p, q      2 and 4 values per pixel (q: TGV): the warm-started duals,
+ *     tpack     4 values per pixel: (t11, t12, t22) of Eq. (12) and I_u,
+ *     rho       float32: rho_c,
+ *     gw        float32 pairs: the tangent at the warped point;
+ *   after the iterations, before the clip: u_pd, v_pd, p_pd, q_pd;
+ *   after the clip: u_next, w_next.
+ * p, q and tpack (and p_pd, q_pd) hold params->storage's values: float32
+ * (8, 16, 16 bytes per pixel), or IEEE half / bfloat16 (4, 8, 8 bytes).
+ * Allocates like vfs_solve_batch (the rig's workspace); synchronises
+ * hip_stream before returning.
+ * Errors: those of vfs_solve_batch; VFS_E_INVALID for a NULL probe, level,
+ * warp or pair out of range, or pitch < W_l. */
+typedef struct {
+    int level, warp, pair;
+    size_t pitch;
+    float *J0, *J1, *u, *w, *v;
+    void *p, *q, *tpack;
+    float *rho, *gw;
+    float *u_pd, *v_pd;
+    void *p_pd, *q_pd;
+    float *u_next, *w_next;
+} vfs_probe;
+vfs_status vfs_solve_probe(vfs_rig* rig, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
+                           const vfs_params* params, const double* betas, const double* etas,
+                           const vfs_probe* probe, void* hip_stream);
+
 /* ---- Steps of the method on caller buffers (device), for step-by-step use
- * and testing; they use FP32 storage whatever params->storage says.  They
+ * and testing; they use FP32 storage whatever params->storage says, except
+ * vfs_step_pd, which takes its duals and tensor pack in params->storage's
+ * format.  They
  * synchronise hip_stream before returning (they allocate a small temporary
  * descriptor, and vfs_step_upsample / vfs_step_triangulate temporary planes).
  * Layout: row-major with a common row pitch of `pitch`
@@ -214,13 +261,17 @@ vfs_status vfs_step_linearise(int width, int height, size_t pitch, const float* 
 /* Eq. (11): `iters` primal-dual iterations from a warp start (ubar = u,
  * vbar = v), with the preconditioned steps of Sec. III-D recomputed from
  * tpack and flags, the resolvent of Eq. (13), and theta per
- * params->theta_gamma.  u, v, p, q are read and overwritten; scratch_* are
+ * params->theta_gamma, run by the kernels and pass schedule of the solves
+ * (params->pass_iters).  u, v, p, q are read and overwritten; scratch_* are
  * caller buffers of the same shapes used as the second copy of the state
- * (the iteration reads one copy and writes the other).  TV mode ignores v, q
+ * (the iteration reads one copy and writes the other).  p, q, tpack and
+ * their scratch hold params->storage's values: float32 (2, 4, 4 per pixel),
+ * or IEEE half / bfloat16 (2, 4, 4 16-bit values per pixel), rounded each
+ * time a launch stores them; u, v, rho stay float32.  TV mode ignores v, q
  * and their scratch (may be NULL). */
-vfs_status vfs_step_pd(int width, int height, size_t pitch, const float* tpack, const float* rho,
-                       const uint8_t* flags, float* u, float* v, float* p, float* q, float* scratch_u,
-                       float* scratch_v, float* scratch_p, float* scratch_q, const vfs_params* params,
+vfs_status vfs_step_pd(int width, int height, size_t pitch, const void* tpack, const float* rho,
+                       const uint8_t* flags, float* u, float* v, void* p, void* q, float* scratch_u,
+                       float* scratch_v, void* scratch_p, void* scratch_q, const vfs_params* params,
                        int iters, void* hip_stream);
 
 /* Sec. IV-B: mask-aware x2 bilinear upsampling of (u, w) from a coarse level

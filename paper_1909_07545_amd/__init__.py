@@ -11,7 +11,7 @@ is no fallback path.
 from ._lib import (  # noqa: F401
     LIB_PATH, Rig, Server, VfsError, default_params, diff_stats, lib, profile_enable, profile_read, rectify,
     rectify_rotations, solve, unrectify,
-    solve_batch, step_energy, step_gradient, step_linearise, step_pd, step_pd_energy, step_rank, step_tensor,
+    solve_batch, solve_probe, step_energy, step_gradient, step_linearise, step_pd, step_pd_energy, step_rank, step_tensor,
     step_triangulate,
     step_upsample, FIELD_TRAJECTORY, FIELD_CALIBRATION, FIELD_FLAGS, F_MASK, F_MX, F_MY, F_DATA, F_EPI,
 )

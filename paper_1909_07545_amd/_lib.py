@@ -40,6 +40,13 @@ class Params(ctypes.Structure):
                 ("pass_iters", ctypes.c_int), ("data_term", ctypes.c_int)]
 
 
+class Probe(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int), ("warp", ctypes.c_int), ("pair", ctypes.c_int),
+                ("pitch", ctypes.c_size_t)] + [(k, ctypes.c_void_p) for k in (
+                    "J0", "J1", "u", "w", "v", "p", "q", "tpack", "rho", "gw", "u_pd", "v_pd", "p_pd", "q_pd",
+                    "u_next", "w_next")]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int),
                 ("use_graphs", ctypes.c_int)]
@@ -72,6 +79,7 @@ def lib():
         L.vfs_rig_field.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]
         L.vfs_solve_batch.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp, _vp, _vp]
+        L.vfs_solve_probe.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
         L.vfs_solve.argtypes = [_vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.vfs_step_tensor.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _vp, _vp, ctypes.c_double,
                                       ctypes.c_double, _vp, _vp]
@@ -216,6 +224,43 @@ def solve_batch(rig: Rig, I0s, I1s, params: dict, betas=None, etas=None, stream=
                                  arr([o["w"] for o in out]), arr([o["depth"] for o in out]),
                                  arr([o["z"] for o in out]), arr([o["valid"] for o in out]), ctypes.byref(p),
                                  bet, et, _stream(stream)))
+    return out
+
+
+_STORAGE_DTYPE = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}
+
+
+def solve_probe(rig: Rig, I0s, I1s, params: dict, level: int, warp: int, pair: int = 0, betas=None, etas=None,
+                stream=None) -> dict:
+    """The state of pair ``pair`` of a batched solve at warp ``warp`` of
+    level ``level`` (vfs_solve_probe): returns CUDA tensors J0, J1, u, w, v,
+    p, q, tpack, rho, gw (after the warp's linearisation), u_pd, v_pd, p_pd,
+    q_pd (after its iterations) and u_next, w_next (after its clip); p, q and
+    tpack in the storage dtype (float32, float16 or bfloat16)."""
+    n = len(I0s)
+    H, W = rig.height, rig.width
+    for t in list(I0s) + list(I1s):
+        _dev_f32(t, (H, W))
+    Hl, Wl = H >> level, W >> level
+    sd = _STORAGE_DTYPE[int(params.get("storage", 0))]
+    tgv = params.get("reg", "tgv") in ("tgv", 0)
+    shapes = dict(J0=(1, torch.float32), J1=(1, torch.float32), u=(1, torch.float32), w=(2, torch.float32),
+                  v=(2, torch.float32), p=(2, sd), q=(4, sd), tpack=(4, sd), rho=(1, torch.float32),
+                  gw=(2, torch.float32), u_pd=(1, torch.float32), v_pd=(2, torch.float32), p_pd=(2, sd),
+                  q_pd=(4, sd), u_next=(1, torch.float32), w_next=(2, torch.float32))
+    out = {}
+    for k, (c, dt) in shapes.items():
+        if not tgv and k in ("v", "q", "v_pd", "q_pd"):
+            continue
+        out[k] = torch.full((Hl, Wl) if c == 1 else (Hl, Wl, c), float("nan"), dtype=dt, device="cuda")
+    pr = Probe(int(level), int(warp), int(pair), Wl, *[out[k].data_ptr() if k in out else None
+                                                        for k in shapes])
+    arr = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])  # noqa: E731
+    pp = _params(params)
+    bet = (ctypes.c_double * n)(*betas) if betas is not None else None
+    et = (ctypes.c_double * n)(*etas) if etas is not None else None
+    _check(lib().vfs_solve_probe(rig.handle, n, arr(I0s), arr(I1s), 4 * W, ctypes.byref(pp), bet, et,
+                                 ctypes.byref(pr), _stream(stream)))
     return out
 
 

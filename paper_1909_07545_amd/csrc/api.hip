@@ -363,8 +363,21 @@ PdArgs pd_args(const Launch& lc, const vfs_params& params)
 
 // Whole method (Algorithm 1 in the pyramid of Sec. IV-B after the
 // pre-rotation of Sec. IV-A, then the triangulation of Sec. III-D).
+// Copies level l of one state plane of a probed pair to dst (level-stacked
+// planes at the level's offset, single-level planes from their start).
+static vfs_status probe_copy(void* dst, const Probe& pr, const Geometry& g, int l, size_t at, bool stacked,
+                             size_t esz, hipStream_t s)
+{
+    if (!dst) return VFS_OK;
+    const char* src = pr.region + at + (stacked ? size_t(g.off[l]) * esz : 0);
+    if (hipMemcpy2DAsync(dst, pr.req.pitch * esz, src, size_t(g.pitch[l]) * esz, size_t(g.W[l]) * esz, g.H[l],
+                         hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(VFS_E_DEVICE, "probe copy failed");
+    return VFS_OK;
+}
+
 vfs_status solve_slots(const Slot* slots, int n, const Geometry& g, const vfs_params& params, hipStream_t s,
-                       vfs_rig* prof)
+                       vfs_rig* prof, const Probe* pr)
 {
     const int L = g.L;
     const bool tgv = params.reg == VFS_TGV;
@@ -398,6 +411,31 @@ vfs_status solve_slots(const Slot* slots, int n, const Geometry& g, const vfs_pa
             const bool last = wv == params.warps;
             if (last && wv == 0) break;
             launch_linearise(lc, wv > 0 ? 1 : 0, last ? 1 : 0, float(params.du_max), xform != 0, st, s);
+            if (pr && l == pr->req.level && wv == pr->req.warp) {
+                // the warp's start: linearised, duals warm-started
+                const PairLayout& y = pr->lay;
+                const vfs_probe& q = pr->req;
+                const size_t e2 = st == ST_F32 ? 8 : 4, e4 = st == ST_F32 ? 16 : 8;
+                vfs_status e = VFS_OK;
+                if (!e) e = probe_copy(q.J0, *pr, g, l, y.J0, true, 4, s);
+                if (!e) e = probe_copy(q.J1, *pr, g, l, y.J1, true, 4, s);
+                if (!e) e = probe_copy(q.u, *pr, g, l, y.u[lc.iu], true, 4, s);
+                if (!e) e = probe_copy(q.w, *pr, g, l, y.w, true, 8, s);
+                if (!e && tgv) e = probe_copy(q.v, *pr, g, l, y.v[lc.iu], true, 8, s);
+                if (!e) e = probe_copy(q.p, *pr, g, l, y.p[lc.ip], true, e2, s);
+                if (!e && tgv) e = probe_copy(q.q, *pr, g, l, y.q[lc.ip], true, e4, s);
+                if (!e) e = probe_copy(q.tpack, *pr, g, l, y.tpack, false, e4, s);
+                if (!e) e = probe_copy(q.rho, *pr, g, l, y.rho, false, 4, s);
+                if (!e) e = probe_copy(q.gw, *pr, g, l, y.gw, false, 8, s);
+                if (e) return e;
+            }
+            if (pr && l == pr->req.level && wv == pr->req.warp + 1) {
+                // the warp's end: clipped and accumulated (by this launch)
+                vfs_status e = probe_copy(pr->req.u_next, *pr, g, l, pr->lay.u[lc.iu], true, 4, s);
+                if (!e) e = probe_copy(pr->req.w_next, *pr, g, l, pr->lay.w, true, 8, s);
+                if (!e && hipGetLastError() != hipSuccess) e = fail(VFS_E_DEVICE, "kernel launch failed");
+                return e;
+            }
             if (last) break;
             // A5: K primal-dual iterations (Eq. (11))
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -411,6 +449,17 @@ vfs_status solve_slots(const Slot* slots, int n, const Geometry& g, const vfs_pa
             lc.iu = iu;
             lc.ip = ip;
             if (e0) prof->launches += np;
+            if (pr && l == pr->req.level && wv == pr->req.warp) {
+                // after the iterations, before the clip
+                const PairLayout& y = pr->lay;
+                const vfs_probe& q = pr->req;
+                const size_t e2 = st == ST_F32 ? 8 : 4, e4 = st == ST_F32 ? 16 : 8;
+                vfs_status e = probe_copy(q.u_pd, *pr, g, l, y.u[iu], true, 4, s);
+                if (!e && tgv) e = probe_copy(q.v_pd, *pr, g, l, y.v[iu], true, 8, s);
+                if (!e) e = probe_copy(q.p_pd, *pr, g, l, y.p[ip], true, e2, s);
+                if (!e && tgv) e = probe_copy(q.q_pd, *pr, g, l, y.q[ip], true, e4, s);
+                if (e) return e;
+            }
         }
     }
     // A8: triangulation and outputs
@@ -529,12 +578,17 @@ vfs_status vfs_rig_field(const vfs_rig* r, int level, int which, void* dst, size
     return VFS_OK;
 }
 
-vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
-                           float* const* u_out, float* const* w_out, float* const* depth_out, float* const* z_out,
-                           uint8_t* const* valid_out, const vfs_params* params, const double* betas,
-                           const double* etas, void* hip_stream)
+}  // extern "C"
+
+namespace {
+
+// Validates a batched solve's arguments, sizes the rig's workspace and
+// writes the pairs' descriptors (outputs may be NULL arrays: a probe).
+vfs_status prepare_batch(vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
+                         float* const* u_out, float* const* w_out, float* const* depth_out, float* const* z_out,
+                         uint8_t* const* valid_out, const vfs_params* params, const double* betas,
+                         const double* etas, bool outputs, hipStream_t s)
 {
-    g_err[0] = 0;
     if (!r) return fail(VFS_E_INVALID, "rig is NULL");
     if (n < 1 || n > kMaxBatch) return fail(VFS_E_INVALID, "n must be in [1, %d]", kMaxBatch);
     vfs_status st = check_params(params);
@@ -543,9 +597,9 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
         return fail(VFS_E_INVALID, "params->levels (%d) differs from the rig's (%d)", params->levels, r->g.L);
     const int W = r->g.W[0];
     if (pitch_bytes % sizeof(float) || pitch_bytes < sizeof(float) * W) return fail(VFS_E_INVALID, "bad pitch");
-    if (!I0 || !I1 || !u_out || !w_out || !depth_out) return fail(VFS_E_INVALID, "NULL array argument");
+    if (!I0 || !I1 || (outputs && (!u_out || !w_out || !depth_out))) return fail(VFS_E_INVALID, "NULL array argument");
     for (int b = 0; b < n; ++b) {
-        if (!I0[b] || !I1[b] || !u_out[b] || !w_out[b] || !depth_out[b])
+        if (!I0[b] || !I1[b] || (outputs && (!u_out[b] || !w_out[b] || !depth_out[b])))
             return fail(VFS_E_INVALID, "NULL buffer for pair %d", b);
         if ((betas && !(betas[b] >= 0.0)) || (etas && !(etas[b] > 0.0)))
             return fail(VFS_E_INVALID, "bad tensor parameters for pair %d", b);
@@ -553,7 +607,6 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
     st = ensure_workspace(r->ws, r->g, n, params->storage, params->reg == VFS_TGV,
                           params->data_term != VFS_DATA_BRIGHTNESS);
     if (st) return st;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
     r->last_stream = s;
     const int ip = int(pitch_bytes / sizeof(float));
     for (int b = 0; b < n; ++b) {
@@ -562,11 +615,11 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
         sl.I1 = I1[b];
         sl.in_pitch = ip;
         sl.out_pitch = ip;
-        sl.u_out = u_out[b];
-        sl.w_out = w_out[b];
-        sl.depth_out = depth_out[b];
-        sl.z_out = z_out ? z_out[b] : nullptr;
-        sl.valid_out = valid_out ? valid_out[b] : nullptr;
+        sl.u_out = outputs ? u_out[b] : nullptr;
+        sl.w_out = outputs ? w_out[b] : nullptr;
+        sl.depth_out = outputs ? depth_out[b] : nullptr;
+        sl.z_out = outputs && z_out ? z_out[b] : nullptr;
+        sl.valid_out = outputs && valid_out ? valid_out[b] : nullptr;
         bind_rig(sl, r);
         bind_state(sl, static_cast<char*>(r->ws.mem) + size_t(b) * r->ws.lay.bytes, r->ws.lay);
         sl.beta = float(betas ? betas[b] : params->beta);
@@ -574,7 +627,49 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
         launch_write_slot(sl, r->ws.slots + b, s);
     }
     r->pass_iters = pd_pass_iters(r->g, params->pass_iters);
+    return VFS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
+                           float* const* u_out, float* const* w_out, float* const* depth_out, float* const* z_out,
+                           uint8_t* const* valid_out, const vfs_params* params, const double* betas,
+                           const double* etas, void* hip_stream)
+{
+    g_err[0] = 0;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    vfs_status st = prepare_batch(r, n, I0, I1, pitch_bytes, u_out, w_out, depth_out, z_out, valid_out, params,
+                                  betas, etas, true, s);
+    if (st) return st;
     return solve_slots(r->ws.slots, n, r->g, *params, s, r);
+}
+
+vfs_status vfs_solve_probe(vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
+                           const vfs_params* params, const double* betas, const double* etas, const vfs_probe* probe,
+                           void* hip_stream)
+{
+    g_err[0] = 0;
+    if (!r || !params || !probe) return fail(VFS_E_INVALID, "NULL argument");
+    if (probe->level < 0 || probe->level >= r->g.L || probe->level >= params->levels)
+        return fail(VFS_E_INVALID, "probe level out of range");
+    if (probe->warp < 0 || probe->warp >= params->warps) return fail(VFS_E_INVALID, "probe warp out of range");
+    if (probe->pair < 0 || probe->pair >= n) return fail(VFS_E_INVALID, "probe pair out of range");
+    if (probe->pitch < size_t(r->g.W[probe->level])) return fail(VFS_E_INVALID, "probe pitch too small");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    vfs_status st = prepare_batch(r, n, I0, I1, pitch_bytes, nullptr, nullptr, nullptr, nullptr, nullptr, params,
+                                  betas, etas, false, s);
+    if (st) return st;
+    Probe pr{};
+    pr.req = *probe;
+    pr.lay = r->ws.lay;
+    pr.region = static_cast<const char*>(r->ws.mem) + size_t(probe->pair) * r->ws.lay.bytes;
+    st = solve_slots(r->ws.slots, n, r->g, *params, s, nullptr, &pr);
+    if (st) return st;
+    HIP_OK(hipStreamSynchronize(s));
+    return VFS_OK;
 }
 
 vfs_status vfs_solve(vfs_rig* rig, const float* I0, const float* I1, size_t pitch_bytes, float* u_out, float* w_out,
@@ -720,8 +815,8 @@ vfs_status vfs_step_linearise(int W, int H, size_t pitch, const float* J0, const
     return VFS_OK;
 }
 
-vfs_status vfs_step_pd(int W, int H, size_t pitch, const float* tpack, const float* rho, const uint8_t* flags, float* u,
-                       float* v, float* p, float* q, float* su, float* sv, float* sp, float* sq,
+vfs_status vfs_step_pd(int W, int H, size_t pitch, const void* tpack, const float* rho, const uint8_t* flags, float* u,
+                       float* v, void* p, void* q, float* su, float* sv, void* sp, void* sq,
                        const vfs_params* params, int iters, void* hip_stream)
 {
     g_err[0] = 0;
@@ -735,10 +830,9 @@ vfs_status vfs_step_pd(int W, int H, size_t pitch, const float* tpack, const flo
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     vfs_params pp = *params;
     pp.iters = iters;
-    pp.storage = VFS_F32;
     const Sched sc = schedule(pp);
     Slot sl{};
-    sl.tpack = const_cast<float*>(tpack);
+    sl.tpack = const_cast<void*>(tpack);
     sl.rho = const_cast<float*>(rho);
     sl.flags[0] = flags;
     sl.u[0] = u;
@@ -755,13 +849,14 @@ vfs_status vfs_step_pd(int W, int H, size_t pitch, const float* tpack, const flo
     int iu, ip;
     run_pd(pd_args(one_launch(os, one_level(W, H, pitch)), pp), sc, iters, iu, ip, s, nullptr, nullptr);
     const size_t plane = pitch * size_t(H);
+    const size_t e2 = pp.storage == VFS_F32 ? 8 : 4, e4 = pp.storage == VFS_F32 ? 16 : 8;
     if (iu) {
         HIP_OK(hipMemcpyAsync(u, su, plane * sizeof(float), hipMemcpyDeviceToDevice, s));
         if (tgv) HIP_OK(hipMemcpyAsync(v, sv, plane * sizeof(float2), hipMemcpyDeviceToDevice, s));
     }
     if (ip) {
-        HIP_OK(hipMemcpyAsync(p, sp, plane * sizeof(float2), hipMemcpyDeviceToDevice, s));
-        if (tgv) HIP_OK(hipMemcpyAsync(q, sq, plane * sizeof(float4), hipMemcpyDeviceToDevice, s));
+        HIP_OK(hipMemcpyAsync(p, sp, plane * e2, hipMemcpyDeviceToDevice, s));
+        if (tgv) HIP_OK(hipMemcpyAsync(q, sq, plane * e4, hipMemcpyDeviceToDevice, s));
     }
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(s));

@@ -101,10 +101,19 @@ void pd_parity(int K, int NP, int& pu, int& pp);
 // PdArgs of a launch with the solver constants of params.
 PdArgs pd_args(const Launch& lc, const vfs_params& params);
 
+// A probed pair of a solve (vfs_solve_probe): the caller's request and where
+// the pair's state lives.
+struct Probe {
+    vfs_probe req;
+    const char* region;     // the pair's state region (device)
+    PairLayout lay;
+};
+
 // Whole method on the n pairs whose descriptors are at slots (device, all of
 // geometry g), enqueued on stream s.  Profiling events, if prof is not NULL
-// and enabled, go to prof.
+// and enabled, go to prof.  With a probe, the solve copies the probed pair's
+// state at the requested warp and stops after that warp's clip.
 vfs_status solve_slots(const Slot* slots, int n, const Geometry& g, const vfs_params& params, hipStream_t s,
-                       vfs_rig* prof);
+                       vfs_rig* prof, const Probe* probe = nullptr);
 
 }  // namespace vfs

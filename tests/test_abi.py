@@ -78,6 +78,7 @@ def test_solve_and_steps_reject_bad_arguments(vfs):
     one = (ctypes.c_void_p * 1)(1)
     assert L.vfs_solve_batch(None, 1, one, one, 256, one, one, one, None, None, ctypes.byref(p), None, None,
                              None) == -1
+    assert L.vfs_solve_probe(None, 1, one, one, 256, ctypes.byref(p), None, None, None, None) == -1
     assert L.vfs_step_tensor(0, 4, 4, one, one, 9.0, 0.85, one, None) == -1
     assert L.vfs_step_tensor(8, 4, 4, one, one, 9.0, 0.85, one, None) == -1           # pitch < width
     bad = vfs._params(dict(vfs.default_params(), alpha1=0.0))

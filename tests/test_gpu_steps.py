@@ -237,6 +237,61 @@ def test_primal_dual(vfs, cid, level, K, reg, tg, npass):
         assert np.max(np.abs(_np(tq) - st["q"])) < tol
 
 
+# Half an ulp at magnitude 1 of the 16-bit formats (FP16: 10 fraction bits,
+# BF16: 7): the most a stored dual component (|p|, |q| <= 1 after the
+# projections) moves when it is rounded.
+HALF_ULP = {1: 2.0 ** -12, 2: 2.0 ** -9}
+
+
+@pytest.mark.parametrize("cid,level,K,reg,storage,npass", [
+    ("c5", 0, 8, "tgv", 1, 3), ("c5", 0, 8, "tgv", 2, 3), ("c5", 0, 7, "tgv", 1, 2), ("c5", 0, 6, "tgv", 2, 2),
+    ("c5", 0, 10, "tv", 1, 3), ("c1", 0, 50, "tgv", 1, 3), ("c1", 0, 50, "tgv", 1, 2), ("c1", 0, 11, "tgv", 2, 3),
+    ("r200", 0, 9, "tgv", 1, 4), ("r200", 1, 11, "tgv", 2, 3), ("r200", 0, 8, "tv", 2, 3), ("c2", 0, 20, "tgv", 1, 2)])
+def test_primal_dual_16bit_storage(vfs, cid, level, K, reg, storage, npass):
+    """K iterations of Eq. (11) with the duals and the tensor pack stored as
+    FP16 / BF16 (FP32 arithmetic, u and v FP32), by the 2-, 3- and
+    4-iteration pass kernels, against the FP64 oracle started from the same
+    16-bit values of p, q, T and I_u.  The GPU rounds p and q each time a
+    launch stores them (at most once per iteration), the oracle never.  One
+    rounding moves a dual component by at most h (half an ulp at magnitude
+    1), and moves the next primal step by at most h too (the preconditioned
+    primal step tau sums the dual changes with weights whose abs-sum is 1);
+    the iteration is nonexpansive in its preconditioned metric, so K
+    roundings add up to at most K h there.  Bars: max |d| <= 2 K h (a factor
+    2 for propagation measured pixel by pixel rather than in that metric),
+    mean |d| <= sqrt(K) h (independent, unbiased roundings), each plus the
+    FP32 bar of the 32-bit test, for u, v, p and q."""
+    import torch
+    tgv = reg == "tgv"
+    flags, T, Iu, rho, u, v, p, q = _pd_state(cid, level, tgv)
+    H, W = u.shape
+    dt = torch.float16 if storage == 1 else torch.bfloat16
+    params = dict(configs.PAPER_PARAMS, levels=1, warps=1, iters=K, reg=reg, storage=storage, pass_iters=npass)
+    tp16 = torch.from_numpy(np.concatenate([T, Iu[..., None]], -1).astype(np.float32)).to(dt).cuda()
+    p16 = torch.from_numpy(p).to(dt).cuda()
+    q16 = torch.from_numpy(q).to(dt).cuda() if tgv else None
+    tu = _t(u)
+    tv = _t(v) if tgv else None
+    back = lambda t: t.float().cpu().numpy().astype(np.float64)  # noqa: E731
+    T0, Iu0, p0 = back(tp16)[..., :3], back(tp16)[..., 3], back(p16)
+    q0 = back(q16) if tgv else None
+    vfs.step_pd(tp16, _t(rho), _t(flags), tu, tv, p16, q16, params, K)
+    torch.cuda.synchronize()
+    m = flags & 1
+    sp, su, sv = oracle.steps(T0, m, params["alpha0"], params["alpha1"], reg)
+    st = oracle.pd_iterations(params, T0, m, sp, su, sv, Iu0, f32(rho), f32(u), f32(v), p0, q0, K)
+    h = HALF_ULP[storage]
+    max_bar, mean_bar = 2 * K * h + 2e-5, np.sqrt(K) * h + 2e-5
+    inside = m.astype(bool)
+    got = dict(u=_np(tu), p=back(p16))
+    if tgv:
+        got.update(v=_np(tv), q=back(q16))
+    for k, g in got.items():
+        d = np.abs(g - st[k])[inside]
+        print(cid, level, K, reg, storage, npass, k, float(d.mean()), float(d.max()), mean_bar, max_bar, flush=True)
+        assert d.max() <= max_bar and d.mean() <= mean_bar, (k, float(d.mean()), float(d.max()))
+
+
 @pytest.mark.parametrize("cid,level", [("c1", 1), ("r200", 1), ("c5", 1)])
 def test_upsample(vfs, cid, level):
     """Mask-aware x2 transfer of (u, w) (Sec. IV-B): within 2e-6."""
