@@ -580,14 +580,11 @@ vfs_status vfs_rig_field(const vfs_rig* r, int level, int which, void* dst, size
 
 }  // extern "C"
 
-namespace {
+namespace vfs {
 
-// Validates a batched solve's arguments, sizes the rig's workspace and
-// writes the pairs' descriptors (outputs may be NULL arrays: a probe).
-vfs_status prepare_batch(vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
-                         float* const* u_out, float* const* w_out, float* const* depth_out, float* const* z_out,
-                         uint8_t* const* valid_out, const vfs_params* params, const double* betas,
-                         const double* etas, bool outputs, hipStream_t s)
+vfs_status check_batch(const vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
+                       float* const* u_out, float* const* w_out, float* const* depth_out, const vfs_params* params,
+                       const double* betas, const double* etas, bool outputs)
 {
     if (!r) return fail(VFS_E_INVALID, "rig is NULL");
     if (n < 1 || n > kMaxBatch) return fail(VFS_E_INVALID, "n must be in [1, %d]", kMaxBatch);
@@ -604,10 +601,15 @@ vfs_status prepare_batch(vfs_rig* r, int n, const float* const* I0, const float*
         if ((betas && !(betas[b] >= 0.0)) || (etas && !(etas[b] > 0.0)))
             return fail(VFS_E_INVALID, "bad tensor parameters for pair %d", b);
     }
-    st = ensure_workspace(r->ws, r->g, n, params->storage, params->reg == VFS_TGV,
-                          params->data_term != VFS_DATA_BRIGHTNESS);
-    if (st) return st;
-    r->last_stream = s;
+    return VFS_OK;
+}
+
+void write_batch_slots(const vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
+                       float* const* u_out, float* const* w_out, float* const* depth_out, float* const* z_out,
+                       uint8_t* const* valid_out, const vfs_params* params, const double* betas,
+                       const double* etas, bool outputs, char* state, const PairLayout& lay, Slot* slots,
+                       hipStream_t s)
+{
     const int ip = int(pitch_bytes / sizeof(float));
     for (int b = 0; b < n; ++b) {
         Slot sl{};
@@ -621,11 +623,32 @@ vfs_status prepare_batch(vfs_rig* r, int n, const float* const* I0, const float*
         sl.z_out = outputs && z_out ? z_out[b] : nullptr;
         sl.valid_out = outputs && valid_out ? valid_out[b] : nullptr;
         bind_rig(sl, r);
-        bind_state(sl, static_cast<char*>(r->ws.mem) + size_t(b) * r->ws.lay.bytes, r->ws.lay);
+        bind_state(sl, state + size_t(b) * lay.bytes, lay);
         sl.beta = float(betas ? betas[b] : params->beta);
         sl.eta = float(etas ? etas[b] : params->eta);
-        launch_write_slot(sl, r->ws.slots + b, s);
+        launch_write_slot(sl, slots + b, s);
     }
+}
+
+}  // namespace vfs
+
+namespace {
+
+// Validates a batched solve's arguments, sizes the rig's workspace and
+// writes the pairs' descriptors (outputs may be NULL arrays: a probe).
+vfs_status prepare_batch(vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
+                         float* const* u_out, float* const* w_out, float* const* depth_out, float* const* z_out,
+                         uint8_t* const* valid_out, const vfs_params* params, const double* betas,
+                         const double* etas, bool outputs, hipStream_t s)
+{
+    vfs_status st = check_batch(r, n, I0, I1, pitch_bytes, u_out, w_out, depth_out, params, betas, etas, outputs);
+    if (st) return st;
+    st = ensure_workspace(r->ws, r->g, n, params->storage, params->reg == VFS_TGV,
+                          params->data_term != VFS_DATA_BRIGHTNESS);
+    if (st) return st;
+    r->last_stream = s;
+    write_batch_slots(r, n, I0, I1, pitch_bytes, u_out, w_out, depth_out, z_out, valid_out, params, betas, etas,
+                      outputs, static_cast<char*>(r->ws.mem), r->ws.lay, r->ws.slots, s);
     r->pass_iters = pd_pass_iters(r->g, params->pass_iters);
     return VFS_OK;
 }

@@ -101,6 +101,19 @@ void pd_parity(int K, int NP, int& pu, int& pp);
 // PdArgs of a launch with the solver constants of params.
 PdArgs pd_args(const Launch& lc, const vfs_params& params);
 
+// Validates the arguments of a batched solve of n pairs on rig r (outputs:
+// whether u_out, w_out, depth_out are required).
+vfs_status check_batch(const vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
+                       float* const* u_out, float* const* w_out, float* const* depth_out, const vfs_params* params,
+                       const double* betas, const double* etas, bool outputs);
+// Writes the descriptors of n pairs (state of pair b at state + b * lay.bytes)
+// to slots (device), stream-ordered on s.
+void write_batch_slots(const vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
+                       float* const* u_out, float* const* w_out, float* const* depth_out, float* const* z_out,
+                       uint8_t* const* valid_out, const vfs_params* params, const double* betas,
+                       const double* etas, bool outputs, char* state, const PairLayout& lay, Slot* slots,
+                       hipStream_t s);
+
 // A probed pair of a solve (vfs_solve_probe): the caller's request and where
 // the pair's state lives.
 struct Probe {

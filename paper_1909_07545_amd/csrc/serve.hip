@@ -161,7 +161,7 @@ struct vfs_server {
     void* pool_mem = nullptr;
     Pool pool;
 
-    std::mutex mu;                      // guards incoming, requests, error, stats read
+    std::mutex mu;                      // guards incoming, requests, error
     std::condition_variable cv;
     std::deque<Request*> incoming;
     std::unordered_map<unsigned long long, std::unique_ptr<Request>> requests;
@@ -180,7 +180,11 @@ struct vfs_server {
     hipEvent_t plain_ev = nullptr;
     Request* plain_cur = nullptr;
 
-    long long ticks = 0, peak_active = 0, active = 0, joins = 0;
+    long long active = 0;               // scheduler thread only
+    // counters written by the scheduler thread and read by vfs_server_stats
+    std::atomic<long long> ticks{0}, peak_active{0}, joins{0}, full_ticks{0};
+    std::atomic<size_t> pool_peak{0};
+    std::atomic<int> nbuckets{0};
     std::thread worker;
 
     ~vfs_server();
@@ -300,6 +304,7 @@ vfs_status make_bucket(vfs_server* sv, const Geometry& g, Bucket*& out)
     if (hipGetLastError() != hipSuccess) return fail(VFS_E_DEVICE, "bucket set-up launch failed");
     out = b.get();
     sv->buckets.push_back(std::move(b));
+    sv->nbuckets.store(int(sv->buckets.size()));
     return VFS_OK;
 }
 
@@ -389,6 +394,7 @@ bool admit(vfs_server* sv)
         }
         size_t off = 0;
         if (!sv->pool.alloc(b->lay.bytes, off)) break;
+        sv->pool_peak.store(sv->pool.peak());
         it = sv->waiting.erase(it);
         r->mem_off = off;
         r->mem_bytes = b->lay.bytes;
@@ -406,7 +412,7 @@ bool admit(vfs_server* sv)
         ss = SlotState{};
         ss.req = r;
         ++sv->active;
-        if (sv->active > sv->peak_active) sv->peak_active = sv->active;
+        if (sv->active > sv->peak_active.load()) sv->peak_active.store(sv->active);
         any = true;
     }
     return any;
@@ -464,7 +470,10 @@ bool launch_tick(vfs_server* sv, Bucket& b)
         int pu, pp;
         enqueue_tick(sv, b, b.stream, full, gl, pu, pp);
     }
-    if (full) ++b.full_ticks;
+    if (full) {
+        ++b.full_ticks;
+        ++sv->full_ticks;
+    }
     if (!b.spare_events.empty()) {
         t.ev = b.spare_events.back();
         b.spare_events.pop_back();
@@ -498,14 +507,19 @@ bool plain_step(vfs_server* sv)
     Workspace* ws = nullptr;
     for (auto& w : sv->plain_ws)
         if (same_geometry(w->g, r->rig->g)) ws = w.get();
-    vfs_status st = VFS_OK;
     if (!ws) {
         sv->plain_ws.push_back(std::make_unique<Workspace>());
         ws = sv->plain_ws.back().get();
-        st = ensure_workspace(*ws, r->rig->g, 1, sv->params.storage, sv->params.reg == VFS_TGV,
-                              sv->params.data_term != VFS_DATA_BRIGHTNESS);
     }
-    if (!st && ws->lay.bytes > sv->cfg.hbm_budget_bytes) st = fail(VFS_E_BUDGET, "request exceeds the HBM budget");
+    const bool tgv = sv->params.reg == VFS_TGV, xform = sv->params.data_term != VFS_DATA_BRIGHTNESS;
+    vfs_status st = VFS_OK;
+    if (make_layout(r->rig->g, sv->params.storage, tgv, xform).bytes > sv->cfg.hbm_budget_bytes)
+        st = fail(VFS_E_BUDGET, "request exceeds the HBM budget");
+    // sizes the workspace on every request (nothing to do once it fits): a
+    // failed allocation leaves it empty, and the next request of this size
+    // allocates again or fails in turn, never runs on an empty workspace
+    if (!st) st = ensure_workspace(*ws, r->rig->g, 1, sv->params.storage, tgv, xform);
+    if (!st && (!ws->mem || !ws->slots)) st = fail(VFS_E_NOMEM, "plain workspace");
     if (st) {
         set_error(sv, st, "plain workspace");
         finish_request(sv, r, Q_FAIL);
@@ -514,7 +528,7 @@ bool plain_step(vfs_server* sv)
     r->t_admit = Clock::now();
     r->state.store(Q_RUN);
     ++sv->active;
-    if (sv->active > sv->peak_active) sv->peak_active = sv->active;
+    if (sv->active > sv->peak_active.load()) sv->peak_active.store(sv->active);
     Slot sl = r->io;
     bind_state(sl, ws->mem, ws->lay);
     launch_write_slot(sl, ws->slots, sv->plain_stream);
@@ -716,15 +730,13 @@ vfs_status vfs_server_wait_all(vfs_server* sv, double timeout_s)
 vfs_status vfs_server_stats(vfs_server* sv, vfs_server_counters* out)
 {
     if (!sv || !out) return fail(VFS_E_INVALID, "NULL argument");
-    std::lock_guard<std::mutex> lk(sv->mu);
-    out->ticks = sv->ticks;
-    out->peak_active = sv->peak_active;
-    out->pool_peak_bytes = sv->pool.peak();
-    out->buckets = int(sv->buckets.size());
-    out->joins = sv->joins;
-    long long full = 0;
-    for (auto& b : sv->buckets) full += b->full_ticks;
-    out->full_ticks = full;
+    // atomics written by the scheduler thread: no scheduler structure is read here
+    out->ticks = sv->ticks.load();
+    out->peak_active = sv->peak_active.load();
+    out->pool_peak_bytes = sv->pool_peak.load();
+    out->buckets = sv->nbuckets.load();
+    out->joins = sv->joins.load();
+    out->full_ticks = sv->full_ticks.load();
     return VFS_OK;
 }
 
