@@ -24,8 +24,10 @@ last warp of every level on the 1280x1024 190-degree room (warps 0, 5, 9 of
 times.  The oracle uses its own trajectory field and flags; the state it
 starts from (pyramid images, u, w, v, p, q) is the GPU's.  The linearisation
 and the tensor of the GPU at the same warp are held to the bars of the step
-tests (I_u 5e-6, rho_c 5e-5, tensor 2e-6), and the pyramid images to the
-oracle's pre-rotation and box filter (1e-5).
+tests (I_u 5e-6, tensor 2e-6, rho_c 5e-5 + 5e-6 |u_w|: rho_c = I1(y) - J0(x)
+- u_w I_u carries u_w times the rounding of I_u, and u_w reaches 150 px on
+the 2048x2048 pairs), and the pyramid images to the oracle's pre-rotation and
+box filter (1e-5).
 
 With 16-bit storage of the duals and the tensor pack (FP32 arithmetic) the
 same comparison is held to the storage bar of 0.05 px mean (first and last
@@ -149,6 +151,8 @@ def _probe_and_compare(vfs, cid, pair, level, warp, storage=0):
                u_pd_max=float(dpd.max()),
                Iu_max=float(np.max(np.abs(tp[..., 3] - o["Iu"]))),
                rho_max=float(np.max(np.abs(_f64(st["rho"]) - o["rho"]))),
+               # rho_c = I1(y) - J0(x) - u_w I_u carries u_w times the rounding of I_u
+               rho_rel=float(np.max(np.abs(_f64(st["rho"]) - o["rho"]) / (5e-5 + 5e-6 * np.abs(_f64(st["u"]))))),
                T_max=float(np.max(np.abs(tp[..., :3] - o["T"]))))
     if warp == 0 and storage == 0:
         J0o, J1o = _pyramid(cid, pair, level)
@@ -161,7 +165,7 @@ def _probe_and_compare(vfs, cid, pair, level, warp, storage=0):
 def _assert_fp32(r):
     assert r["u_mean"] <= FP32_MEAN and r["u_max"] <= FP32_MAX, r
     assert r["w_mean"] <= FP32_MEAN and r["w_max"] <= FP32_MAX, r
-    assert r["T_max"] <= 2e-6 and r["Iu_max"] <= 5e-6 and r["rho_max"] <= 5e-5, r
+    assert r["T_max"] <= 2e-6 and r["Iu_max"] <= 5e-6 and r["rho_rel"] <= 1.0, r
     if "J0_max" in r:
         assert r["J0_max"] <= 1e-6 and r["J1_max"] <= 1e-5, r
 
