@@ -241,7 +241,8 @@ def solve_probe(rig: Rig, I0s, I1s, params: dict, level: int, warp: int, pair: i
     H, W = rig.height, rig.width
     for t in list(I0s) + list(I1s):
         _dev_f32(t, (H, W))
-    Hl, Wl = H >> level, W >> level
+    lv = min(max(int(level), 0), rig.levels - 1)   # plane sizes only: the library checks the level
+    Hl, Wl = H >> lv, W >> lv
     sd = _STORAGE_DTYPE[int(params.get("storage", 0))]
     tgv = params.get("reg", "tgv") in ("tgv", 0)
     shapes = dict(J0=(1, torch.float32), J1=(1, torch.float32), u=(1, torch.float32), w=(2, torch.float32),
