@@ -37,6 +37,9 @@ BYTES_PER_PIX_LAUNCH = 93
 BYTES_PER_PIX_LAUNCH_16 = 61
 TEXTBOOK_BYTES_PER_PIX_ITER = 117
 HBM_PEAK_GBS = 8000.0
+# the best streaming copy measured on this MI355X (one float per thread,
+# 4 GiB buffers): what an access pattern like the pass's can reach
+BEST_COPY_GBS = 6240.0
 VALU_PEAK_LANE_INSTR_S = 256 * 4 * 16 * 2.4e9
 
 
@@ -132,19 +135,48 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     value = pix_iter / (dt / args.steps) / 1e6
 
+    # the same steps replayed from the graph the library captures at the first
+    # solve of this configuration (no timing events inside)
+    outs_g = vfs.solve_batch(R, I0s, I1s, params, betas=betas, etas=etas)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        outs_g = vfs.solve_batch(R, I0s, I1s, params, betas=betas, etas=etas, out=outs_g)
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - t0
+    same = all(torch.equal(a[k], b[k]) for a, b in zip(outs, outs_g) for k in ("u", "w", "depth"))
+    graph = {"value": round(pix_iter / (dtg / args.steps) / 1e6, 1), "ms_per_step": round(1e3 * dtg / args.steps, 2),
+             "outputs_equal_eager": same}
+    log(f"bench: {args.steps} graph replays in {dtg:.3f} s (outputs equal to eager: {same})")
+    del outs_g
+
     W, H = cfg["width"], cfg["height"]
     avg_launch_s = (pd_ms / pd_launches) / 1e3 if pd_launches else float("nan")
+    # algorithmic bytes of one launch: 117 B per pixel-iteration (the textbook
+    # state of Eq. (11) read and written once per iteration) x the pixel-
+    # iterations one launch carries; the pass keeps the intermediate
+    # iterations in registers, so this rate is an effective one and exceeds
+    # the HBM peak
+    textbook_bytes = TEXTBOOK_BYTES_PER_PIX_ITER * iters_per_launch * W * H * n
+    achieved = textbook_bytes / avg_launch_s / 1e9
+    # bytes the pass must move at least: every state plane read and written once per launch
     bytes_per_launch = BYTES_PER_PIX_LAUNCH * W * H * n
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    effective = TEXTBOOK_BYTES_PER_PIX_ITER * iters_per_launch * W * H * n / avg_launch_s / 1e9
+    compulsory = bytes_per_launch / avg_launch_s / 1e9
+    traffic = measured_traffic(args.config)
+    counters = traffic / avg_launch_s / 1e9 if traffic else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.config),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "frac_kind": "effective: 117 B per pixel-iteration x pixel-iterations per launch",
                 "kernel": f"level-0 primal-dual pass ({iters_per_launch} iterations of Eq. (11) per launch, "
                           f"{'pd2_kernel' if iters_per_launch == 2 else 'pdn_kernel'}<TGV>)",
                 "iters_per_launch": iters_per_launch,
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": pd_launches,
-                "bytes_per_launch": bytes_per_launch,
-                "effective_textbook_GBs": round(effective, 1),
+                "textbook_bytes_per_launch": textbook_bytes,
+                "compulsory_bytes_per_launch": bytes_per_launch,
+                "compulsory_GBs": round(compulsory, 1),
+                "frac_compulsory": round(compulsory / HBM_PEAK_GBS, 4),
+                "counters_GBs": round(counters, 1) if counters else None,
+                "frac_counters": round(counters / HBM_PEAK_GBS, 4) if counters else None,
                 "level0_Mpix_iter_s": round(iters_per_launch * W * H * n / avg_launch_s / 1e6, 1)}
 
     # The same launch against the vector-issue peak: a wave64 vector
@@ -181,6 +213,15 @@ def main():
                 "mean_abs_u_diff_vs_fp32_px": round(du, 5)}
         log(f"bench: fp16 storage {args.steps} steps in {dt16:.3f} s")
 
+    if alu is not None:
+        # the roof that binds: HBM by the counters (against the best streaming
+        # copy measured on this GPU) or vector issue, whichever is closer to its peak
+        hbm_near = roofline["counters_GBs"] / BEST_COPY_GBS if roofline["counters_GBs"] else None
+        roofline["binding"] = ("vector issue" if hbm_near is None or alu["frac"] > hbm_near else "hbm") + \
+            f" (vector issue at {alu['frac']:.2f} of peak" + \
+            (f", HBM traffic at {hbm_near:.2f} of the best copy measured, {BEST_COPY_GBS:.0f} GB/s)" if hbm_near
+             else ")")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, rig, pairs[0], tens[0], params, args.cpu_seconds)
@@ -209,6 +250,7 @@ def main():
                    "iters": cfg["iters"], "pix_iter_per_step": pix_iter},
         "roofline": roofline,
         "alu": alu,
+        "graph_replay": graph,
         "cpu_baseline": cpu,
         "fp16_storage": fp16,
         "serving": serve,
@@ -371,10 +413,19 @@ def measured_traffic(config):
 
 def cpu_baseline(cfg, rig, pair, tens, params, seconds):
     """The FP64 oracle's primal-dual iterations (the hot loop) on pair 0's
-    full-resolution level-0 problem, for a bounded number of iterations."""
+    full-resolution level-0 problem, for a bounded number of iterations, on
+    all host threads and on one; beside it the oracle's whole method
+    (Algorithm 1 in the pyramid, triangulation) on the 128x128 plane and the
+    640x480 room in full, all threads."""
+    import ctypes
+
     import numpy as np
 
     import oracle
+    from synth import configs, scene
+
+    gomp = ctypes.CDLL("libgomp.so.1")
+    all_threads = gomp.omp_get_max_threads()
 
     I0 = pair[0].astype(np.float64)
     I1 = pair[1].astype(np.float64)
@@ -401,12 +452,36 @@ def cpu_baseline(cfg, rig, pair, tens, params, seconds):
     oracle.pd_iterations(params, T, m, sp, tu, tv, Iu, rho, st["u"], st["v"], st["p"], st["q"], k,
                          ubar=st["ubar"], vbar=st["vbar"])
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     val = W * H * k / dt / 1e6
-    log(f"bench: cpu baseline {k} iterations in {dt:.1f} s")
-    return {"value": round(val, 2), "unit": "Mpix-iter/s", "cores": threads, "kind": "oracle",
+    log(f"bench: cpu baseline {k} iterations in {dt:.1f} s on {all_threads} threads")
+    # one thread: a tenth of the iterations
+    k1 = max(2, k // 10)
+    gomp.omp_set_num_threads(1)
+    t0 = time.perf_counter()
+    oracle.pd_iterations(params, T, m, sp, tu, tv, Iu, rho, st["u"], st["v"], st["p"], st["q"], k1,
+                         ubar=st["ubar"], vbar=st["vbar"])
+    dt1 = time.perf_counter() - t0
+    gomp.omp_set_num_threads(all_threads)
+    log(f"bench: cpu baseline {k1} iterations in {dt1:.1f} s on 1 thread")
+    whole = {}
+    for cid in ("c1", "c2"):
+        c = configs.get(cid)
+        d = scene.make_inputs(cid, 1)
+        rg = d["rig"]
+        t0 = time.perf_counter()
+        oracle.solve(rg["cam0"], rg["cam1"], rg["R"], rg["t"], configs.solver_params(c),
+                     d["I0"][0].astype(np.float64), d["I1"][0].astype(np.float64))
+        dtw = time.perf_counter() - t0
+        whole[cid] = {"Mpix_iter_s": round(configs.pix_iters(c) / dtw / 1e6, 2), "seconds": round(dtw, 2),
+                      "workload": f"{c['name']}: {c['width']}x{c['height']}, {c['levels']} levels x "
+                                  f"{c['warps']} warps x {c['iters']} iters, whole method"}
+        log(f"bench: cpu baseline whole method {cid} in {dtw:.1f} s")
+    return {"value": round(val, 2), "unit": "Mpix-iter/s", "cores": all_threads, "kind": "oracle",
             "sample": f"{k} primal-dual iterations of Eq. (11) on pair 0's full {W}x{H} level-0 problem "
-                      f"(FP64 C oracle, OpenMP over rows), {dt:.1f} s"}
+                      f"(FP64 C oracle, OpenMP over rows), {dt:.1f} s",
+            "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "one_core": {"value": round(W * H * k1 / dt1 / 1e6, 2), "iterations": k1, "seconds": round(dt1, 1)},
+            "whole_method_all_cores": whole}
 
 
 if __name__ == "__main__":

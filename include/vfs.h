@@ -164,6 +164,19 @@ vfs_status vfs_solve_batch(vfs_rig* rig, int n, const float* const* I0, const fl
                            const vfs_params* params, const double* betas, const double* etas,
                            void* hip_stream);
 
+/* Graph replay of the direct solves (the fixed iteration counts of Sec. IV-C
+ * make a solve one fixed sequence of launches).  With enable = 1 (the
+ * default) the first vfs_solve / vfs_solve_batch of a launch configuration
+ * (batch size n and every solver parameter but beta and eta) on a rig
+ * captures its launches into a HIP graph, and later solves of that
+ * configuration replay it: one graph launch on hip_stream, after the pairs'
+ * descriptors are written.  Results are the same as eager launches, bit for
+ * bit.  The rig keeps up to 8 graphs (all dropped when a ninth is needed)
+ * until vfs_rig_destroy; enable = 0 drops them and launches eagerly.  Solves
+ * with profiling on (vfs_profile_enable) always launch eagerly.
+ * Errors: VFS_E_INVALID (NULL rig). */
+vfs_status vfs_rig_graphs(vfs_rig* rig, int enable);
+
 /* One pair: vfs_solve_batch with n = 1. */
 vfs_status vfs_solve(vfs_rig* rig, const float* I0, const float* I1, size_t pitch_bytes, float* u_out,
                      float* w_out, float* depth_out, float* z_out, uint8_t* valid_out,

@@ -80,6 +80,7 @@ def lib():
         L.vfs_solve_batch.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp, _vp, _vp]
         L.vfs_solve_probe.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
+        L.vfs_rig_graphs.argtypes = [_vp, ctypes.c_int]
         L.vfs_solve.argtypes = [_vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.vfs_step_tensor.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _vp, _vp, ctypes.c_double,
                                       ctypes.c_double, _vp, _vp]
@@ -191,6 +192,10 @@ class Rig:
             self.close()
         except Exception:
             pass
+
+    def use_graphs(self, enable: bool = True):
+        """Replay captured graphs for this rig's solves (vfs_rig_graphs)."""
+        _check(lib().vfs_rig_graphs(self._h, int(bool(enable))))
 
     def field(self, level: int, which: int, stream=None) -> torch.Tensor:
         H, W = self.height >> level, self.width >> level

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "runtime.h"
 
@@ -93,11 +94,17 @@ vfs_rig::~vfs_rig()
         if (flags[l]) (void)hipFree(flags[l]);
     }
     if (calib) (void)hipFree(calib);
+    if (radial) (void)hipFree(radial);
     if (geom_dev) (void)hipFree(geom_dev);
     for (auto& e : events) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    for (auto& gr : graphs) {
+        (void)hipGraphExecDestroy(gr.exec);
+        (void)hipGraphDestroy(gr.graph);
+    }
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }
 
 namespace vfs {
@@ -539,6 +546,27 @@ vfs_status vfs_rig_create(const vfs_camera* cam0, const vfs_camera* cam1, const 
     auto cleanup = [&](vfs_status e) { delete r; return e; };
     if (hipGetDevice(&r->device) != hipSuccess) return cleanup(fail(VFS_E_DEVICE, "hipGetDevice failed"));
     prepare_pd();
+    // camera 0 and the baseline in single precision for the triangulation,
+    // with the radial table of its back-projection computed here in double
+    // precision (once per rig)
+    TriGeom& tg = g.tri;
+    tg.model = g.cam0.model;
+    tg.fx = float(g.cam0.fx);
+    tg.fy = float(g.cam0.fy);
+    tg.cx = float(g.cam0.cx);
+    tg.cy = float(g.cam0.cy);
+    tg.th_lim = float(g.cam0.th_lim);
+    tg.dtheta = float(g.cam0.th_lim / kRadial);
+    for (int a = 0; a < 3; ++a) tg.C[a] = float(g.C[a]);
+    std::vector<float2> table(kRadial + 1);
+    const double dth = g.cam0.th_lim / kRadial;
+    for (int k = 0; k <= kRadial; ++k)
+        table[k] = make_float2(float(cam_rd(g.cam0, k * dth)), float(dth * cam_drd(g.cam0, k * dth)));
+    if (hipMalloc(&r->radial, table.size() * sizeof(float2)) != hipSuccess)
+        return cleanup(fail(VFS_E_NOMEM, "radial table"));
+    if (hipMemcpy(r->radial, table.data(), table.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(VFS_E_DEVICE, "copying the radial table"));
+    tg.radial = r->radial;
     if (hipMalloc(&r->geom_dev, sizeof(RigGeom)) != hipSuccess) return cleanup(fail(VFS_E_NOMEM, "rig geometry"));
     if (hipMemcpyAsync(r->geom_dev, &g, sizeof(RigGeom), hipMemcpyHostToDevice, s) != hipSuccess)
         return cleanup(fail(VFS_E_DEVICE, "copying rig geometry"));
@@ -653,9 +681,77 @@ vfs_status prepare_batch(vfs_rig* r, int n, const float* const* I0, const float*
     return VFS_OK;
 }
 
+// Solver parameters that change a solve's launches (beta and eta travel in
+// the pair descriptors).
+bool same_launches(const vfs_params& a, const vfs_params& b)
+{
+    return a.levels == b.levels && a.warps == b.warps && a.iters == b.iters && a.reg == b.reg &&
+           a.lambda == b.lambda && a.alpha0 == b.alpha0 && a.alpha1 == b.alpha1 && a.du_max == b.du_max &&
+           a.theta_gamma == b.theta_gamma && a.storage == b.storage && a.pass_iters == b.pass_iters &&
+           a.data_term == b.data_term;
+}
+
+constexpr size_t kMaxGraphs = 8;
+
+void drop_graphs(vfs_rig* r)
+{
+    for (auto& gr : r->graphs) {
+        (void)hipGraphExecDestroy(gr.exec);
+        (void)hipGraphDestroy(gr.graph);
+    }
+    r->graphs.clear();
+}
+
+// The whole method on the rig's workspace as one graph launch on s: the
+// launches of solve_slots are captured (on a stream of the rig's) the first
+// time a launch configuration occurs and replayed after.  The pair
+// descriptors, written on s before this, carry the images, outputs and
+// tensor parameters, so one graph serves any inputs of that configuration.
+vfs_status solve_graph(vfs_rig* r, int n, const vfs_params& p, hipStream_t s)
+{
+    vfs_rig::SolveGraph* hit = nullptr;
+    for (auto& gr : r->graphs)
+        if (gr.n == n && gr.mem == r->ws.mem && gr.slots == r->ws.slots && same_launches(gr.params, p)) hit = &gr;
+    if (!hit) {
+        if (r->graphs.size() >= kMaxGraphs) drop_graphs(r);
+        if (!r->capture_stream && hipStreamCreateWithFlags(&r->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(VFS_E_DEVICE, "hipStreamCreate");
+        vfs_rig::SolveGraph gr{};
+        gr.params = p;
+        gr.n = n;
+        gr.mem = r->ws.mem;
+        gr.slots = r->ws.slots;
+        if (hipStreamBeginCapture(r->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(VFS_E_DEVICE, "hipStreamBeginCapture");
+        const vfs_status st = solve_slots(r->ws.slots, n, r->g, p, r->capture_stream, nullptr);
+        const hipError_t ec = hipStreamEndCapture(r->capture_stream, &gr.graph);
+        if (st || ec != hipSuccess) {
+            if (ec == hipSuccess) (void)hipGraphDestroy(gr.graph);
+            return st ? st : fail(VFS_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        }
+        if (hipGraphInstantiateWithFlags(&gr.exec, gr.graph, 0) != hipSuccess) {
+            (void)hipGraphDestroy(gr.graph);
+            return fail(VFS_E_DEVICE, "hipGraphInstantiate");
+        }
+        r->graphs.push_back(gr);
+        hit = &r->graphs.back();
+    }
+    HIP_OK(hipGraphLaunch(hit->exec, s));
+    return VFS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+vfs_status vfs_rig_graphs(vfs_rig* r, int enable)
+{
+    g_err[0] = 0;
+    if (!r) return fail(VFS_E_INVALID, "rig is NULL");
+    r->use_graphs = enable != 0;
+    if (!r->use_graphs) drop_graphs(r);
+    return VFS_OK;
+}
 
 vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const float* const* I1, size_t pitch_bytes,
                            float* const* u_out, float* const* w_out, float* const* depth_out, float* const* z_out,
@@ -667,6 +763,7 @@ vfs_status vfs_solve_batch(vfs_rig* r, int n, const float* const* I0, const floa
     vfs_status st = prepare_batch(r, n, I0, I1, pitch_bytes, u_out, w_out, depth_out, z_out, valid_out, params,
                                   betas, etas, true, s);
     if (st) return st;
+    if (r->use_graphs && !r->profile) return solve_graph(r, n, *params, s);
     return solve_slots(r->ws.slots, n, r->g, *params, s, r);
 }
 

@@ -47,7 +47,7 @@ __global__ void energy_kernel(Launch lc, float lambda, float a0, float a1, int t
     Pick pk;
     double e = 0.0;
     if (pick(lc, z, pk)) {
-        const Slot& sl = lc.slots[z];
+        const Slot& sl = lc.slots[pk.slot];
         const int l = pk.l, W = lc.g.W[l], H = lc.g.H[l], pitch = lc.g.pitch[l];
         const int j = blockIdx.x * 64 + (threadIdx.x & 63);
         const int i = blockIdx.y * kRows + (threadIdx.x >> 6);

@@ -87,7 +87,7 @@ __global__ void prerotate_kernel(Launch lc)
     Pick pk;
     int j, i;
     if (!pixel_of(lc, pk, j, i)) return;
-    const Slot& sl = lc.slots[blockIdx.z];
+    const Slot& sl = lc.slots[pk.slot];
     const int W = lc.g.W[0], H = lc.g.H[0], pitch = lc.g.pitch[0];
     const size_t o = (size_t)i * pitch + j;
     const float2 c = sl.calib[o];
@@ -101,7 +101,7 @@ __global__ void downsample_kernel(Launch lc)
     Pick pk;
     int j, i;
     if (!pixel_of(lc, pk, j, i)) return;
-    const Slot& sl = lc.slots[blockIdx.z];
+    const Slot& sl = lc.slots[pk.slot];
     const int l = pk.l;
     const int fp = lc.g.pitch[l - 1];
     const size_t fo = lc.g.off[l - 1] + (size_t)(2 * i) * fp + 2 * j;
@@ -118,7 +118,7 @@ __global__ void tensor_kernel(Launch lc)
     Pick pk;
     int j, i;
     if (!pixel_of(lc, pk, j, i)) return;
-    const Slot& sl = lc.slots[blockIdx.z];
+    const Slot& sl = lc.slots[pk.slot];
     const int l = pk.l, W = lc.g.W[l], H = lc.g.H[l], pitch = lc.g.pitch[l];
     const uint8_t* flags = sl.flags[l];
     float4 t = make_float4(1.f, 0.f, 1.f, 0.f);
@@ -153,7 +153,7 @@ __global__ void linearise_kernel(Launch lc, int clip, int clip_only, float du_ma
     Pick pk;
     int j, i;
     if (!pixel_of(lc, pk, j, i)) return;
-    const Slot& sl = lc.slots[blockIdx.z];
+    const Slot& sl = lc.slots[pk.slot];
     const int l = pk.l, W = lc.g.W[l], H = lc.g.H[l], pitch = lc.g.pitch[l];
     const long long off = lc.g.off[l];
     const size_t o = (size_t)i * pitch + j;       // single-level planes
@@ -218,7 +218,7 @@ __global__ void transform_kernel(Launch lc)
     Pick pk;
     int j, i;
     if (!pixel_of(lc, pk, j, i)) return;
-    const Slot& sl = lc.slots[blockIdx.z];
+    const Slot& sl = lc.slots[pk.slot];
     const int l = pk.l, W = lc.g.W[l], H = lc.g.H[l], pitch = lc.g.pitch[l];
     const long long off = lc.g.off[l];
     const float* img[2] = {sl.J0 + off, sl.J1 + off};
@@ -254,7 +254,7 @@ __global__ void upsample_kernel(Launch lc, int tgv)
     Pick pk;
     int j, i;
     if (!pixel_of(lc, pk, j, i)) return;
-    const Slot& sl = lc.slots[blockIdx.z];
+    const Slot& sl = lc.slots[pk.slot];
     const int l = pk.l, lc1 = l + 1;
     const int Wc = lc.g.W[lc1], Hc = lc.g.H[lc1], cp = lc.g.pitch[lc1];
     const uint8_t* flags_c = sl.flags[lc1];
@@ -300,7 +300,7 @@ __global__ void zero_state_kernel(Launch lc, int tgv)
     Pick pk;
     int j, i;
     if (!pixel_of(lc, pk, j, i)) return;
-    const Slot& sl = lc.slots[blockIdx.z];
+    const Slot& sl = lc.slots[pk.slot];
     const int pu = par_u(lc, pk), pp = par_p(lc, pk);
     const size_t o = lc.g.off[pk.l] + (size_t)i * lc.g.pitch[pk.l] + j;
     sl.u[pu][o] = 0.f;
@@ -312,34 +312,89 @@ __global__ void zero_state_kernel(Launch lc, int tgv)
     }
 }
 
+// Polar angle of a ray of camera 0 at normalised radius rd (single
+// precision): equidistant in closed form, the other radially symmetric
+// models from the rig's radial table -- the interval of rd by bisection,
+// then two Newton steps on the cubic Hermite interpolant of r_d there --
+// saturating at the model's limit like the set-up's inverse.
+__device__ inline float theta32(const TriGeom& t, float rd)
+{
+    if (t.model == 1) return fminf(rd, t.th_lim);
+    const float2* R = t.radial;
+    if (!(rd > 0.f)) return 0.f;
+    if (rd >= R[kRadial].x) return t.th_lim;
+    int lo = 0, hi = kRadial;             // R[lo].x <= rd < R[hi].x
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (R[mid].x <= rd) lo = mid;
+        else hi = mid;
+    }
+    // the interpolant as r_d = a.x + s (m + s (c2 + s c3)), s in [0, 1]: the
+    // residual is formed from the small differences rd - a.x and b.x - a.x
+    // (exact in float), not from values of the size of r_d
+    const float2 a = R[lo], b = R[hi];
+    const float dr = b.x - a.x, e = rd - a.x;
+    const float c2 = 3.f * dr - 2.f * a.y - b.y, c3 = a.y + b.y - 2.f * dr;
+    float s = e / dr;
+    for (int it = 0; it < 2; ++it) {
+        const float h = s * (a.y + s * (c2 + s * c3)) - e;
+        const float dh = a.y + s * (2.f * c2 + 3.f * s * c3);
+        s = fminf(fmaxf(s - h / dh, 0.f), 1.f);
+    }
+    return (float(lo) + s) * t.dtheta;
+}
+
+// Unit ray of camera 0 at normalised coordinates (mx, my) = (x - c) / f.
+__device__ inline float3 ray32(const TriGeom& t, float mx, float my)
+{
+    if (t.model == 0) {
+        const float n = rsqrtf(mx * mx + my * my + 1.f);
+        return make_float3(mx * n, my * n, n);
+    }
+    const float rd = sqrtf(mx * mx + my * my);
+    if (!(rd > 0.f)) return make_float3(0.f, 0.f, 1.f);
+    float sn, cs;
+    sincosf(theta32(t, rd), &sn, &cs);
+    const float k = sn / rd;
+    return make_float3(k * mx, k * my, cs);
+}
+
+__device__ inline float3 cross3(float3 a, float3 b)
+{
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ inline float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
 // Closest approach of the rays a = pi0^-1(x) from the origin and
-// b = pi0^-1(x + w) from C = -t', in double precision (level 0).
+// b = pi0^-1(x + w) from C = -t' (level 0), in single precision: with
+// n = a x b, the ranges along a and b are d0 = ((C x b) . n) / |n|^2 and
+// d1 = ((C x a) . n) / |n|^2 (the cross products avoid the cancellation of
+// 1 - (a . b)^2 for nearly parallel rays).
 __global__ void triangulate_kernel(Launch lc)
 {
     Pick pk;
     int j, i;
     if (!pixel_of(lc, pk, j, i)) return;
-    const Slot& sl = lc.slots[blockIdx.z];
-    const RigGeom& g = *sl.geom;
+    const Slot& sl = lc.slots[pk.slot];
+    const TriGeom& g = sl.geom->tri;
     const size_t o = (size_t)i * lc.g.pitch[0] + j;
     const size_t oo = (size_t)i * sl.out_pitch + j;
     const float2 ww = sl.w[o];
     if (sl.u_out) sl.u_out[oo] = sl.u[par_u(lc, pk)][o];
     if (sl.w_out) { sl.w_out[2 * oo] = ww.x; sl.w_out[2 * oo + 1] = ww.y; }
-    double a[3], bb[3];
-    cam_ray(g.cam0, j, i, a);
-    cam_ray(g.cam0, double(j) + double(ww.x), double(i) + double(ww.y), bb);
-    const double ab = a[0] * bb[0] + a[1] * bb[1] + a[2] * bb[2];
-    const double aC = a[0] * g.C[0] + a[1] * g.C[1] + a[2] * g.C[2];
-    const double bC = bb[0] * g.C[0] + bb[1] * g.C[1] + bb[2] * g.C[2];
-    const double den = 1.0 - ab * ab;
+    const float px = float(j) - g.cx, py = float(i) - g.cy;
+    const float3 a = ray32(g, px / g.fx, py / g.fy);
+    const float3 b = ray32(g, (px + ww.x) / g.fx, (py + ww.y) / g.fy);
+    const float3 C = make_float3(g.C[0], g.C[1], g.C[2]);
+    const float3 n = cross3(a, b);
+    const float den = dot3(n, n);
     float depth = __builtin_inff(), z = __builtin_inff();
     uint8_t ok = 0;
-    if (den > 1e-12 && (sl.flags[0][o] & F_DATA)) {
-        const double d0 = (aC - ab * bC) / den, d1 = (ab * aC - bC) / den;
-        if (d0 > 0.0 && d1 > 0.0) {
-            depth = float(d0);
-            z = float(d0 * a[2]);
+    if (den > 1e-12f && (sl.flags[0][o] & F_DATA)) {
+        const float d0 = dot3(cross3(C, b), n) / den, d1 = dot3(cross3(C, a), n) / den;
+        if (d0 > 0.f && d1 > 0.f) {
+            depth = d0;
+            z = d0 * a.z;
             ok = 1;
         }
     }

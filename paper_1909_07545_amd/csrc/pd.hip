@@ -134,7 +134,7 @@ __device__ inline bool planes_of(const PdArgs& a, int z, Planes& P)
 {
     Pick pk;
     if (!pick(a.lc, z, pk)) return false;
-    const Slot& sl = a.lc.slots[z];
+    const Slot& sl = a.lc.slots[pk.slot];
     const int l = pk.l;
     const long long off = a.lc.g.off[l];
     const int pu = (a.lc.iu ^ int(pk.flip)) & 1, pp = (a.lc.ip ^ int(pk.flip >> 1)) & 1;

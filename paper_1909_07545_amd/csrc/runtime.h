@@ -58,8 +58,23 @@ struct vfs_rig {
     float2* gamma[vfs::kMaxLevels] = {};
     uint8_t* flags[vfs::kMaxLevels] = {};
     float2* calib = nullptr;
+    float2* radial = nullptr;           // camera 0's radial table (TriGeom)
     int device = 0;
     vfs::Workspace ws;                  // used by vfs_solve / vfs_solve_batch
+
+    // captured direct solves: one HIP graph per launch configuration (batch
+    // size, solver parameters, workspace), replayed by later solves
+    struct SolveGraph {
+        vfs_params params;
+        int n;
+        const void* mem;
+        const vfs::Slot* slots;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<SolveGraph> graphs;
+    hipStream_t capture_stream = nullptr;
+    bool use_graphs = true;
 
     // level-0 primal-dual timing
     bool profile = false;

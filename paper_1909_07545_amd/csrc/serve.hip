@@ -125,6 +125,10 @@ struct Tick {
     std::vector<int> finishing;     // slots whose request completes with this tick
 };
 
+// Launch sizes of a bucket's ticks: a tick's launches cover its active slots
+// (their control words come first), rounded up to one of these sizes.
+constexpr int kTickSizes = 6;    // 1, 2, 4, 8, 16, 32 (at most the bucket's slots)
+
 struct Bucket {
     Geometry g{};
     PairLayout lay{};
@@ -132,10 +136,14 @@ struct Bucket {
     Slot* slots_dev = nullptr;
     Ctrl* ctrl_dev = nullptr;
     hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;  // graphs are captured here, launched on `stream`
+    int sizes[kTickSizes] = {};
+    int nsizes = 0;
     // [gl][0]: warp step only, [gl][1]: every stage; gl: the finest level
-    // among the tick's slots (the warp step's grids cover that level)
-    hipGraph_t graph[kMaxLevels][2] = {};
-    hipGraphExec_t exec[kMaxLevels][2] = {};
+    // among the tick's slots (the warp step's grids cover that level);
+    // [k]: launch size sizes[k]
+    hipGraph_t graph[kMaxLevels][2][kTickSizes] = {};
+    hipGraphExec_t exec[kMaxLevels][2][kTickSizes] = {};
     int par_u = 0, par_p = 0;       // parity change of one tick's primal-dual launches
     std::vector<SlotState> slot;
     std::deque<Tick> inflight;
@@ -205,8 +213,8 @@ void set_error(vfs_server* sv, vfs_status st, const char* what)
 // by its control word (see the comment at the top of this file).  Without
 // `full`, only the warp step (for ticks where no slot starts, changes level
 // or finishes).  The warp step's grids cover level gl, the finest level
-// among the tick's slots.
-void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int gl, int& par_u, int& par_p)
+// among the tick's slots; the launches cover n control words.
+void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int gl, int n, int& par_u, int& par_p)
 {
     const vfs_params& P = sv->params;
     const bool tgv = P.reg == VFS_TGV;
@@ -216,7 +224,7 @@ void enqueue_tick(vfs_server* sv, Bucket& b, hipStream_t s, bool full, int gl, i
     Launch lc{};
     lc.slots = b.slots_dev;
     lc.ctrl = b.ctrl_dev;
-    lc.n = b.S;
+    lc.n = n;
     lc.tick = 1;
     lc.g = b.g;
     lc.lev = -1;
@@ -277,29 +285,35 @@ vfs_status make_bucket(vfs_server* sv, const Geometry& g, Bucket*& out)
     b->lay = make_layout(g, sv->params.storage, sv->params.reg == VFS_TGV, sv->params.data_term != VFS_DATA_BRIGHTNESS);
     b->S = sv->cfg.max_slots;
     b->slot.resize(b->S);
+    for (int k = 1; b->nsizes < kTickSizes; k *= 2) {
+        b->sizes[b->nsizes++] = k < b->S ? k : b->S;
+        if (k >= b->S) break;
+    }
     if (hipMalloc(&b->slots_dev, sizeof(Slot) * b->S) != hipSuccess ||
         hipMalloc(&b->ctrl_dev, sizeof(Ctrl) * kMaxBatch) != hipSuccess)
         return fail(VFS_E_NOMEM, "bucket tables");
-    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess)
         return fail(VFS_E_DEVICE, "hipStreamCreate");
     // every slot starts inactive
     CtrlBlock cb{};
     launch_write_ctrl(cb, kMaxBatch, b->ctrl_dev, b->stream);
+    // parity change of one tick (the launch sequence of every tick, any size)
+    pd_parity(sv->params.iters, pd_pass_iters(b->g, sv->params.pass_iters), b->par_u, b->par_p);
     if (sv->cfg.use_graphs) {
         prepare_pd();
         for (int gl = 0; gl < g.L; ++gl)
-            for (int full = 0; full < 2; ++full) {
-                if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-                    return fail(VFS_E_DEVICE, "hipStreamBeginCapture");
-                enqueue_tick(sv, *b, b->stream, full != 0, gl, b->par_u, b->par_p);
-                if (hipStreamEndCapture(b->stream, &b->graph[gl][full]) != hipSuccess)
-                    return fail(VFS_E_DEVICE, "hipStreamEndCapture");
-                if (hipGraphInstantiateWithFlags(&b->exec[gl][full], b->graph[gl][full], 0) != hipSuccess)
-                    return fail(VFS_E_DEVICE, "hipGraphInstantiate");
-            }
-    } else {
-        // parity change of one tick (same launch sequence as the graph)
-        pd_parity(sv->params.iters, pd_pass_iters(b->g, sv->params.pass_iters), b->par_u, b->par_p);
+            for (int full = 0; full < 2; ++full)
+                for (int k = 0; k < b->nsizes; ++k) {
+                    int pu, pp;
+                    if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                        return fail(VFS_E_DEVICE, "hipStreamBeginCapture");
+                    enqueue_tick(sv, *b, b->capture, full != 0, gl, b->sizes[k], pu, pp);
+                    if (hipStreamEndCapture(b->capture, &b->graph[gl][full][k]) != hipSuccess)
+                        return fail(VFS_E_DEVICE, "hipStreamEndCapture");
+                    if (hipGraphInstantiateWithFlags(&b->exec[gl][full][k], b->graph[gl][full][k], 0) != hipSuccess)
+                        return fail(VFS_E_DEVICE, "hipGraphInstantiate");
+                }
     }
     if (hipGetLastError() != hipSuccess) return fail(VFS_E_DEVICE, "bucket set-up launch failed");
     out = b.get();
@@ -321,13 +335,15 @@ void bucket_destroy(Bucket& b)
     for (auto& t : b.inflight) (void)hipEventDestroy(t.ev);
     for (auto e : b.spare_events) (void)hipEventDestroy(e);
     for (int l = 0; l < kMaxLevels; ++l)
-        for (int k = 0; k < 2; ++k) {
-            if (b.exec[l][k]) (void)hipGraphExecDestroy(b.exec[l][k]);
-            if (b.graph[l][k]) (void)hipGraphDestroy(b.graph[l][k]);
-        }
+        for (int f = 0; f < 2; ++f)
+            for (int k = 0; k < kTickSizes; ++k) {
+                if (b.exec[l][f][k]) (void)hipGraphExecDestroy(b.exec[l][f][k]);
+                if (b.graph[l][f][k]) (void)hipGraphDestroy(b.graph[l][f][k]);
+            }
     if (b.slots_dev) (void)hipFree(b.slots_dev);
     if (b.ctrl_dev) (void)hipFree(b.ctrl_dev);
     if (b.stream) (void)hipStreamDestroy(b.stream);
+    if (b.capture) (void)hipStreamDestroy(b.capture);
 }
 
 void finish_request(vfs_server* sv, Request* r, int state)
@@ -425,11 +441,13 @@ bool launch_tick(vfs_server* sv, Bucket& b)
     CtrlBlock cb{};
     Tick t;
     bool work = false, full = false;
-    int gl = L - 1;
+    int gl = L - 1, n = 0;
     for (int z = 0; z < b.S; ++z) {
         SlotState& ss = b.slot[z];
-        Ctrl& c = cb.c[z];
         if (!ss.req || ss.draining) continue;
+        // the active slots' control words come first: the tick's launches cover only them
+        Ctrl& c = cb.c[n++];
+        c.slot = uint8_t(z);
         uint8_t ops;
         if (!ss.started) {
             ss.started = true;
@@ -462,13 +480,15 @@ bool launch_tick(vfs_server* sv, Bucket& b)
         work = true;
     }
     if (!work) return false;
-    launch_write_ctrl(cb, b.S, b.ctrl_dev, b.stream);
+    int k = 0;
+    while (b.sizes[k] < n) ++k;         // launch size: the smallest one that covers the active slots
+    launch_write_ctrl(cb, b.sizes[k], b.ctrl_dev, b.stream);
     if (sv->cfg.use_graphs) {
-        if (hipGraphLaunch(b.exec[gl][full ? 1 : 0], b.stream) != hipSuccess)
+        if (hipGraphLaunch(b.exec[gl][full ? 1 : 0][k], b.stream) != hipSuccess)
             set_error(sv, VFS_E_DEVICE, "hipGraphLaunch failed");
     } else {
         int pu, pp;
-        enqueue_tick(sv, b, b.stream, full, gl, pu, pp);
+        enqueue_tick(sv, b, b.stream, full, gl, b.sizes[k], pu, pp);
     }
     if (full) {
         ++b.full_ticks;

@@ -159,6 +159,22 @@ __host__ __device__ inline Cam cam_level(const Cam& c, int l)
 }
 
 // ----------------------------------------------------------------- rig geometry (device side)
+// Radial table of camera 0 for the per-pair back-projection in single
+// precision: entry k holds r_d(theta_k) and dtheta r_d'(theta_k) at theta_k =
+// k dtheta, dtheta = th_lim / kRadial, computed in double precision once per
+// rig; the inverse of r_d is the cubic Hermite interpolant of these values
+// inverted by Newton steps.
+constexpr int kRadial = 4096;
+
+// Camera 0 and the baseline in single precision, for the triangulation.
+struct TriGeom {
+    int model;
+    float fx, fy, cx, cy;
+    float th_lim, dtheta;
+    float C[3];                 // -t'
+    const float2* radial;       // kRadial + 1 entries (device; not used by pinhole / equidistant)
+};
+
 struct RigGeom {
     Cam cam0, cam1;
     double R[9];        // X1 = R X0 + t
@@ -168,6 +184,7 @@ struct RigGeom {
     double half1;       // FOV1 / 2 (radians)
     double cos_guard;   // cos of the epipole guard angle
     double eps;         // step along t' of the trajectory-field construction
+    TriGeom tri;
 };
 
 // A camera and a virtual pinhole view rotated against it (X_v = Rv X_cam).
@@ -290,11 +307,12 @@ struct Slot {
     float beta, eta;
 };
 
-// Per-tick control of a slot in the serving loop (written between graph
-// replays).  ops: the stages of the tick the slot takes part in; level: the
-// level of the tick's warp step; warp: its index in the level; flip: parity
-// of the slot's double-buffered state relative to the launch's (bit 0 u/v,
-// bit 1 p/q).
+// Per-tick control of one pair of a serving tick (written between graph
+// replays; entry z of a tick's launches covers slot `slot` of the bucket).
+// ops: the stages of the tick the slot takes part in; level: the level of
+// the tick's warp step; warp: its index in the level; flip: parity of the
+// slot's double-buffered state relative to the launch's (bit 0 u/v, bit 1
+// p/q).
 enum : uint8_t {
     OP_START = 1u,      // pre-rotation, pyramids, zero state at the coarsest level
     OP_NEWLEVEL = 2u,   // close level+1 (final accumulate) and transfer to level
@@ -307,14 +325,15 @@ struct Ctrl {
     int8_t level;
     uint8_t ops;
     uint8_t flip;
-    uint8_t pad;
+    uint8_t slot;
     int32_t warp;
 };
 
 // Which pairs a launch covers and at which level.  tick = 0: pairs 0..n-1, all
-// at level lev, parity (iu, ip).  tick = 1 (serving): pair z takes part if
-// ctrl[z].ops & op, at level lev if lev >= 0 else ctrl[z].level + dl, with
-// parity (iu, ip) ^ ctrl[z].flip.  The grid covers the level-gl size.
+// at level lev, parity (iu, ip).  tick = 1 (serving): entry z covers slot
+// ctrl[z].slot, which takes part if ctrl[z].ops & op, at level lev if lev >= 0
+// else ctrl[z].level + dl, with parity (iu, ip) ^ ctrl[z].flip.  The grid
+// covers the level-gl size.
 struct Launch {
     const Slot* slots;
     const Ctrl* ctrl;
@@ -331,6 +350,7 @@ struct Pick {
     int l;
     unsigned flip;
     int warp;
+    int slot;       // the pair's descriptor: lc.slots[slot]
 };
 
 __device__ inline bool pick(const Launch& lc, int z, Pick& pk)
@@ -340,6 +360,7 @@ __device__ inline bool pick(const Launch& lc, int z, Pick& pk)
         pk.l = lc.lev;
         pk.flip = 0u;
         pk.warp = -1;
+        pk.slot = z;
         return true;
     }
     const Ctrl c = lc.ctrl[z];
@@ -347,6 +368,7 @@ __device__ inline bool pick(const Launch& lc, int z, Pick& pk)
     pk.l = lc.lev >= 0 ? lc.lev : c.level + lc.dl;
     pk.flip = c.flip;
     pk.warp = c.warp;
+    pk.slot = c.slot;
     return pk.l >= 0 && pk.l < lc.g.L;
 }
 

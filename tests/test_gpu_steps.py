@@ -310,10 +310,22 @@ def test_upsample(vfs, cid, level):
     assert np.max(np.abs(_np(wf) - wo)) < 2e-6
 
 
-@pytest.mark.parametrize("cid", ["c2", "c5", "ucm", "eucm"])
+@pytest.mark.parametrize("cid", ["c1", "c2", "c5", "ucm", "eucm"])
 def test_triangulate(vfs, cid):
-    """Closest-approach depth in double precision from the same float32 warp
-    vectors: valid flags identical, depth and Z within float32 rounding."""
+    """Closest-approach depth in single precision (rays from the rig's
+    radial table, built in double precision at set-up) against the FP64
+    oracle on the same float32 warp vectors.  A float32 ray is off by about
+    1e-7 rad (the rounding of the table, of the polar angle and of the pixel
+    position x + w).  When the two rays turn by such an angle, a point seen
+    at ranges d0 and d1 under the parallax angle |a x b| moves by about
+    (d0 + d1) 1e-7 / |a x b|, so the relative error of d0 is about
+    (1 + d1 / d0) 1e-7 / |a x b|: the bar is 1e-5 + 5e-7 (1 + d1 / d0) /
+    |a x b|, with d1 from the oracle's rays (d1 / d0 is large for points
+    within a few baselines of camera 0).  Validity is decided by
+    |a x b|^2 > 1e-12 and the signs of the two ranges; it must be identical
+    wherever the oracle's |a x b|^2 is at least 4e-12 (outside the band where
+    float32 rounding reaches the threshold: |w| below about 1e-3 px); inside
+    the band both answers are correct."""
     import torch
     rig = _rig(cid)
     cfg = configs.get(cid)
@@ -330,21 +342,26 @@ def test_triangulate(vfs, cid):
     dv = oracle.data_valid(cam, rig["cam1"], rig["R"], rig["t"], 0)
     do, zo, vo = oracle.triangulate(cam, rig["R"], rig["t"], f32(w), dv)
     vg = _np(valid).astype(bool)
-    assert np.array_equal(vg, vo)
-    # where the rays meet at a usable angle (|w| >= 0.05 px) the double-precision
-    # results agree to float32 output rounding plus the double rounding of the
-    # rays amplified by the closest approach's division by 1 - (a.b)^2 (both
-    # sides evaluate it in FP64 with different operation orders); closer to
-    # parallel rays only validity is compared
-    ok = vo & (np.linalg.norm(w, axis=-1) >= 0.05)
-    assert ok.sum() > 0.5 * vo.sum()
     jj, ii = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
-    x0 = np.stack([jj[ok], ii[ok]], -1)
+    x0 = np.stack([jj.ravel(), ii.ravel()], -1)
     ra = oracle.unproject(cam, x0)
-    rb = oracle.unproject(cam, x0 + f32(w)[ok])
-    den = 1.0 - np.sum(ra * rb, -1) ** 2
-    bar = 1e-6 + 1e-14 / den
+    rb = oracle.unproject(cam, x0 + f32(w).reshape(-1, 2))
+    n = np.cross(ra, rb)
+    nn = np.linalg.norm(n, axis=-1).reshape(H, W)
+    # range along b of the closest approach, from the oracle's rays (for the bar)
+    C = -(np.asarray(rig["R"]).T @ np.asarray(rig["t"]))
+    d1 = (np.sum(np.cross(np.broadcast_to(C, ra.shape), ra) * n, -1) /
+          np.maximum(np.sum(n * n, -1), 1e-300)).reshape(H, W)
+    band = nn ** 2 < 4e-12
+    flips = vg != vo
+    print(cid, "validity flips", int(flips.sum()), "of them in the rounding band", int((flips & band).sum()),
+          "band pixels", int(band.sum()), flush=True)
+    assert not (flips & ~band).any()
+    ok = vo & vg
+    assert ok.sum() > 0.5 * vo.sum()
+    bar = 1e-5 + 5e-7 * (1.0 + np.abs(d1[ok]) / do[ok]) / nn[ok]
     rel = np.abs(_np(depth)[ok] - do[ok]) / do[ok]
+    print(cid, "depth rel. error max", float(rel.max()), "share of bar", float((rel / bar).max()), flush=True)
     assert np.all(rel <= bar), (rel.max(), (rel / bar).max())
     assert np.all(np.abs(_np(z)[ok] - zo[ok]) / do[ok] <= bar)
-    assert np.all(np.isinf(_np(depth)[~vo]))
+    assert np.all(np.isinf(_np(depth)[~vg]))
