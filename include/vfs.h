@@ -177,6 +177,27 @@ vfs_status vfs_solve_batch(vfs_rig* rig, int n, const float* const* I0, const fl
  * Errors: VFS_E_INVALID (NULL rig). */
 vfs_status vfs_rig_graphs(vfs_rig* rig, int enable);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * vfs_solve_batch with the same arguments, kernels and results, but the
+ * pairs' solve state and descriptors live in a fixed device array of the
+ * library (VFS_NOALLOC_SCRATCH_BYTES, held on each device the call runs on
+ * until the process ends) instead of the rig's workspace; no device memory
+ * is allocated or freed.  The state of n pairs must fit: n x (about 149
+ * bytes per level-0 pixel in FP32, 109 with 16-bit storage) plus 16 KB of
+ * descriptors, e.g. one 640x480 FP32 pair or 26 128x128 pairs; a larger
+ * request returns VFS_E_BUDGET before any device work.  Every call on a
+ * device shares that device's array: calls that overlap on one device (on
+ * different streams or threads) race and must not be made.  The solve
+ * writes every state value before reading it, so nothing carries over from
+ * the previous call.  Errors: those of vfs_solve_batch, VFS_E_BUDGET. */
+#define VFS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+vfs_status vfs_solve_batch_noalloc(vfs_rig* rig, int n, const float* const* I0, const float* const* I1,
+                                   size_t pitch_bytes, float* const* u_out, float* const* w_out,
+                                   float* const* depth_out, float* const* z_out, uint8_t* const* valid_out,
+                                   const vfs_params* params, const double* betas, const double* etas,
+                                   void* hip_stream);
+
 /* One pair: vfs_solve_batch with n = 1. */
 vfs_status vfs_solve(vfs_rig* rig, const float* I0, const float* I1, size_t pitch_bytes, float* u_out,
                      float* w_out, float* depth_out, float* z_out, uint8_t* valid_out,

@@ -79,6 +79,8 @@ def lib():
         L.vfs_rig_field.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]
         L.vfs_solve_batch.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp, _vp, _vp]
+        L.vfs_solve_batch_noalloc.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp,
+                                              _vp, _vp, _vp, _vp]
         L.vfs_solve_probe.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]
         L.vfs_rig_graphs.argtypes = [_vp, ctypes.c_int]
         L.vfs_solve.argtypes = [_vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -267,6 +269,25 @@ def solve_probe(rig: Rig, I0s, I1s, params: dict, level: int, warp: int, pair: i
     et = (ctypes.c_double * n)(*etas) if etas is not None else None
     _check(lib().vfs_solve_probe(rig.handle, n, arr(I0s), arr(I1s), 4 * W, ctypes.byref(pp), bet, et,
                                  ctypes.byref(pr), _stream(stream)))
+    return out
+
+
+def solve_batch_noalloc(rig: Rig, I0s, I1s, params: dict, out: list, betas=None, etas=None, stream=None):
+    """vfs_solve_batch_noalloc: the batched solve with the library's fixed
+    device scratch instead of an allocated workspace.  ``out``: one dict of
+    pre-allocated output tensors (u, w, depth, z, valid) per pair."""
+    n = len(I0s)
+    H, W = rig.height, rig.width
+    for t in list(I0s) + list(I1s):
+        _dev_f32(t, (H, W))
+    arr = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])  # noqa: E731
+    p = _params(params)
+    bet = (ctypes.c_double * n)(*betas) if betas is not None else None
+    et = (ctypes.c_double * n)(*etas) if etas is not None else None
+    _check(lib().vfs_solve_batch_noalloc(rig.handle, n, arr(I0s), arr(I1s), 4 * W, arr([o["u"] for o in out]),
+                                         arr([o["w"] for o in out]), arr([o["depth"] for o in out]),
+                                         arr([o["z"] for o in out]), arr([o["valid"] for o in out]),
+                                         ctypes.byref(p), bet, et, _stream(stream)))
     return out
 
 
