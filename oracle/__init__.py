@@ -75,6 +75,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vfs_oracle.c")
+_ABI = os.path.join(_HERE, "vfso.c")      # the library's calls over the oracle (host pointers)
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 MODELS = {"pinhole": 0, "equidistant": 1, "kb": 2, "kannala_brandt": 2, "unified": 3, "ucm": 3,
@@ -98,10 +99,11 @@ class _Params(ctypes.Structure):
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (C11, strict IEEE double, OpenMP over rows)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                         os.path.getmtime(_ABI)):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, _SRC, _ABI, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

@@ -50,10 +50,6 @@ namespace vfs {
 
 namespace {
 
-#ifndef VFS_PD_DPP
-#define VFS_PD_DPP 1
-#endif
-
 constexpr int kLanes = 64;
 constexpr int kWaves = 4;            // wavefronts per workgroup
 constexpr int kCols = kLanes - 2;    // owned columns per wavefront, one-iteration modes
@@ -77,7 +73,6 @@ constexpr long long kRoundsForShort = 4;
 constexpr int kXcds = 8;
 
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-#if VFS_PD_DPP
 // whole-wavefront shifts by one lane (DPP wave_shr:1 / wave_shl:1); the lane
 // without a source receives 0 -- always a halo lane whose result is unused
 __device__ inline float from_left(float x)
@@ -88,10 +83,6 @@ __device__ inline float from_right(float x)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, false));
 }
-#else
-__device__ inline float from_left(float x) { return __shfl_up(x, 1, kLanes); }
-__device__ inline float from_right(float x) { return __shfl_down(x, 1, kLanes); }
-#endif
 
 struct Row {
     float u;

@@ -5,8 +5,8 @@ by pytest; it needs a GPU and a few minutes of host CPU).
       FP32 / FP16 / BF16 storage of one 1280x1024 190-degree pair (6 levels x
       10 warps x 150 iterations) and of pair 0 of the 2048x2048 200-degree
       batch (7 x 15 x 200): displacement and depth error against the oracle,
-      next to the conditioning floor (the FP32 solve of the input perturbed
-      by 1e-6 relative, against the unperturbed FP32 solve).
+      next to the conditioning floor (the oracle's own solve of the input
+      perturbed by 1e-6 relative, against its unperturbed solve).
 
   python -m tests.accuracy_study serving OUT.json
       The serving workload's solver settings (10 warps x 50 iterations,
@@ -89,12 +89,14 @@ def precision():
         log(f"precision: {cid} oracle solve took {time.perf_counter() - t:.1f} s")
         m = oracle.mask0(rig["cam0"]).astype(bool)
         row = {name: _errors(out, o, m) for name, out in outs.items()}
+        # conditioning floor, from the oracle alone: its own solve of I0 perturbed by 1e-6 relative
+        # (the size of float32's per-step differences) against its unperturbed solve
         rng = np.random.default_rng(0)
-        I0p = (I0.astype(np.float64) * (1 + 1e-6 * rng.standard_normal(I0.shape))).astype(np.float32)
-        outp = vfs.solve(R, torch.from_numpy(I0p).cuda(), t1, params)
-        d = np.abs(outp["u"].cpu().numpy() - outs["f32"]["u"].cpu().numpy())[m]
-        row["floor_f32_input_1e-6"] = {"u_mean": float(d.mean()), "u_p99": float(np.percentile(d, 99)),
-                                       "u_max": float(d.max())}
+        I0p = I0.astype(np.float64) * (1 + 1e-6 * rng.standard_normal(I0.shape))
+        op = oracle.solve(rig["cam0"], rig["cam1"], rig["R"], rig["t"], params, I0p, I1.astype(np.float64))
+        d = np.abs(op["u"] - o["u"])[m]
+        row["floor_oracle_input_1e-6"] = {"u_mean": float(d.mean()), "u_p99": float(np.percentile(d, 99)),
+                                          "u_max": float(d.max())}
         table[cid] = row
         log(f"precision: {cid} {json.dumps(row)}")
     return {"precision": table}
