@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--pass-iters", type=int, default=0,
                     help="primal-dual iterations per pass (0: the library's choice by pair size)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving study")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the graph-replay timing (for counter-collection runs of the profiler)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving study (prints its JSON)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-rates", type=lambda v: [float(x) for x in v.split(",")], default=[0.5, 0.8, 1.0, 1.5],
@@ -137,18 +139,9 @@ def main():
 
     # the same steps replayed from the graph the library captures at the first
     # solve of this configuration (no timing events inside)
-    outs_g = vfs.solve_batch(R, I0s, I1s, params, betas=betas, etas=etas)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        outs_g = vfs.solve_batch(R, I0s, I1s, params, betas=betas, etas=etas, out=outs_g)
-    torch.cuda.synchronize()
-    dtg = time.perf_counter() - t0
-    same = all(torch.equal(a[k], b[k]) for a, b in zip(outs, outs_g) for k in ("u", "w", "depth"))
-    graph = {"value": round(pix_iter / (dtg / args.steps) / 1e6, 1), "ms_per_step": round(1e3 * dtg / args.steps, 2),
-             "outputs_equal_eager": same}
-    log(f"bench: {args.steps} graph replays in {dtg:.3f} s (outputs equal to eager: {same})")
-    del outs_g
+    graph = None
+    if not args.no_graph:
+        graph = graph_replay(vfs, torch, R, I0s, I1s, params, betas, etas, outs, pix_iter, args.steps)
 
     W, H = cfg["width"], cfg["height"]
     avg_launch_s = (pd_ms / pd_launches) / 1e3 if pd_launches else float("nan")
@@ -256,6 +249,23 @@ def main():
         "serving": serve,
     }
     print(json.dumps(line), flush=True)
+
+
+def graph_replay(vfs, torch, R, I0s, I1s, params, betas, etas, outs, pix_iter, steps):
+    """The timed steps again, replayed from the HIP graph the library captures
+    at the first solve of the configuration; outputs compared with the eager
+    solve's."""
+    outs_g = vfs.solve_batch(R, I0s, I1s, params, betas=betas, etas=etas)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        outs_g = vfs.solve_batch(R, I0s, I1s, params, betas=betas, etas=etas, out=outs_g)
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - t0
+    same = all(torch.equal(a[k], b[k]) for a, b in zip(outs, outs_g) for k in ("u", "w", "depth"))
+    log(f"bench: {steps} graph replays in {dtg:.3f} s (outputs equal to eager: {same})")
+    return {"value": round(pix_iter / (dtg / steps) / 1e6, 1), "ms_per_step": round(1e3 * dtg / steps, 2),
+            "outputs_equal_eager": same}
 
 
 def _pct(xs, q):
