@@ -155,7 +155,7 @@ def main():
     # bytes the pass must move at least: every state plane read and written once per launch
     bytes_per_launch = BYTES_PER_PIX_LAUNCH * W * H * n
     compulsory = bytes_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(args.config)
+    traffic = measured_traffic(args.config, iters_per_launch)
     counters = traffic / avg_launch_s / 1e9 if traffic else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -175,14 +175,15 @@ def main():
     # The same launch against the vector-issue peak: a wave64 vector
     # instruction occupies one of 256 CUs x 4 SIMDs of 16 lanes for 4 cycles at
     # 2.4 GHz (packed FP32 instructions are not used), i.e. 39.3 T lane-instructions/s.
-    valu = measured_valu(args.config)
+    valu = measured_valu(args.config, iters_per_launch)
     alu = None
     if valu is not None and pd_launches:
         peak_li = VALU_PEAK_LANE_INSTR_S / 1e12
         achieved_li = valu * 64 / avg_launch_s / 1e12
         alu = {"bound": "alu", "achieved": round(achieved_li, 2), "peak": round(peak_li, 2),
                "unit": "T lane-instructions/s", "frac": round(achieved_li / peak_li, 4),
-               "valu_wave64_per_launch": valu, "source": "profiles/pdn3_kernel_batch2048_valu.json"}
+               "valu_wave64_per_launch": valu,
+               "source": f"profiles/pdn{iters_per_launch}_kernel_batch2048_valu.json"}
 
     fp16 = None
     if not args.no_fp16:
@@ -390,12 +391,13 @@ def serving_study(args, log_prefix="serving"):
     return res
 
 
-def measured_valu(config):
-    """Wave64 vector instructions per launch of the dominant kernel from the
-    committed rocprofv3 counter summary (SQ_INSTS_VALU), or None if there is
-    none for this workload or the kernel source has changed since."""
+def measured_valu(config, n):
+    """Wave64 vector instructions per launch of the dominant kernel (n
+    iterations per pass) from the committed rocprofv3 counter summary
+    (SQ_INSTS_VALU), or None if there is none for this workload or the
+    kernel source has changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pdn3_kernel_batch2048_valu.json")
+    path = os.path.join(ROOT, "profiles", f"pdn{n}_kernel_batch2048_valu.json")
     if config != "c5" or not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -405,13 +407,13 @@ def measured_valu(config):
     return rec["valu_wave64_instructions_per_launch"]
 
 
-def measured_traffic(config):
-    """HBM bytes per launch of the dominant kernel (the level-0 three-iteration
-    pass) from the committed rocprofv3 counter summary (FETCH_SIZE +
+def measured_traffic(config, n):
+    """HBM bytes per launch of the dominant kernel (the level-0 pass of n
+    iterations) from the committed rocprofv3 counter summary (FETCH_SIZE +
     WRITE_SIZE, scaled by a plain copy), or None if there is none for this
     workload or the kernel source has changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pdn3_kernel_batch2048_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"pdn{n}_kernel_batch2048_traffic.json")
     if config != "c5" or not os.path.exists(path):
         return None
     rec = json.load(open(path))

@@ -254,17 +254,23 @@ vfs_status check_params(const vfs_params* p)
 }
 
 // Iterations per pass of the dominant primal-dual launches for pairs whose
-// level 0 is g's, unless `requested` (2, 3 or 4) fixes it.  Measured on
-// MI355X: three iterations per pass are faster where the passes are
-// bandwidth-bound (2048x2048 pairs: 4 wavefronts per SIMD), two where the
-// launches are latency-bound (pairs up to 1280x1024, alone or in serving
-// buckets).  The choice depends on the pair's size only, not on how many
-// pairs share a launch, so that a pair's result does not depend on its batch
-// (16-bit storage rounds the duals at pass boundaries).
-int pd_pass_iters(const Geometry& g, int requested)
+// level 0 is g's, in a storage mode, unless `requested` (2, 3 or 4) fixes it.
+// Measured on MI355X (8 pairs of 2048x2048, whole solve): where the passes
+// are bandwidth-bound (2048x2048 pairs), four iterations per pass in FP32
+// (138.3 Gpix-iter/s against 131.0 with three; the four-iteration kernel
+// keeps its row constants in LDS and runs four wavefronts per SIMD) and
+// three with 16-bit storage (162.4 against 146.0 with four: that kernel is
+// bound by vector issue, and a fourth iteration adds halo work); two where
+// the launches are latency-bound (pairs up to 1280x1024, alone or in serving
+// buckets).  The choice depends on the pair's size and the storage only, not
+// on how many pairs share a launch, so that a pair's result does not depend
+// on its batch (16-bit storage rounds the duals at pass boundaries; in FP32
+// the pass depth changes no result).
+int pd_pass_iters(const Geometry& g, int requested, int storage)
 {
     if (requested >= 2 && requested <= 4) return requested;
-    return (long long)g.W[0] * g.H[0] >= (2ll << 20) ? 3 : 2;
+    if ((long long)g.W[0] * g.H[0] < (2ll << 20)) return 2;
+    return storage == VFS_F32 ? 4 : 3;
 }
 
 void pd_parity(int K, int NP, int& pu, int& pp)
@@ -364,7 +370,7 @@ PdArgs pd_args(const Launch& lc, const vfs_params& params)
     pa.lambda = float(params.lambda);
     pa.tgv = params.reg == VFS_TGV ? 1 : 0;
     pa.storage = params.storage;
-    pa.pass = pd_pass_iters(lc.g, params.pass_iters);
+    pa.pass = pd_pass_iters(lc.g, params.pass_iters, params.storage);
     return pa;
 }
 
@@ -677,7 +683,7 @@ vfs_status prepare_batch(vfs_rig* r, int n, const float* const* I0, const float*
     r->last_stream = s;
     write_batch_slots(r, n, I0, I1, pitch_bytes, u_out, w_out, depth_out, z_out, valid_out, params, betas, etas,
                       outputs, static_cast<char*>(r->ws.mem), r->ws.lay, r->ws.slots, s);
-    r->pass_iters = pd_pass_iters(r->g, params->pass_iters);
+    r->pass_iters = pd_pass_iters(r->g, params->pass_iters, params->storage);
     return VFS_OK;
 }
 

@@ -664,6 +664,72 @@ template <> struct TensorRaw<ST_F32> {
     __device__ static float4 identity() { return make_float4(1.f, 0.f, 1.f, 0.f); }
 };
 
+// The row constants (tensor pack as stored, rho_c) of the last D rows of a
+// downward march: a register delay line shifted at every step, or a ring in
+// LDS, one per wavefront, where the row entering at a step takes slot h, row
+// r - d sits at slot (h + d) mod D and h steps back by one per step.  The
+// ring holds the four-iteration kernels' eight rows out of the registers:
+// 122 VGPRs instead of 140 in FP32 (four wavefronts per SIMD instead of
+// three, with 40 KB of LDS per workgroup), and 2048x2048 pairs then run four
+// iterations per pass faster than three (measured; see pd_pass_iters).  The
+// three-iteration kernels keep their six rows in registers: the ring saves
+// them no wavefront and its index arithmetic costs as much as the moves it
+// saves (measured: equal times).
+template <typename TRaw, int D, bool RING> struct RowConsts {
+    TRaw t[D];
+    float rho[D];
+    __device__ void init(TRaw id)
+    {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            t[d] = id;
+            rho[d] = 0.f;
+        }
+    }
+    __device__ void set_first(TRaw v) { t[0] = v; }
+    __device__ void push(TRaw v, float r)
+    {
+#pragma unroll
+        for (int d = D - 1; d > 0; --d) {
+            t[d] = t[d - 1];
+            rho[d] = rho[d - 1];
+        }
+        t[0] = v;
+        rho[0] = r;
+    }
+    __device__ TRaw tens(int d) const { return t[d]; }
+    __device__ float rh(int d) const { return rho[d]; }
+};
+
+template <typename TRaw, int D> struct RowConsts<TRaw, D, true> {
+    TRaw (*t)[kLanes];     // this wavefront's D slots of 64 lanes in LDS
+    float (*rho)[kLanes];
+    int h, ln;
+    __device__ int at(int d) const
+    {
+        const int k = h + d;
+        return k >= D ? k - D : k;
+    }
+    __device__ void init(TRaw id)
+    {
+        h = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            t[d][ln] = id;
+            rho[d][ln] = 0.f;
+        }
+    }
+    __device__ void set_first(TRaw v) { t[h][ln] = v; }
+    __device__ void push(TRaw v, float r)
+    {
+        h = h == 0 ? D - 1 : h - 1;
+        t[h][ln] = v;
+        rho[h][ln] = r;
+    }
+    __device__ TRaw tens(int d) const { return t[at(d)][ln]; }
+    __device__ float rh(int d) const { return rho[at(d)][ln]; }
+};
+
 // Whether a march computes each row's step-size bases once, when the row
 // enters, and carries them in a delay line beside the tensor, or at every use.
 // Both give the same values.  Carried where the registers fit without losing
@@ -687,14 +753,18 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
     // tensor pack as stored (16-bit modes keep it packed until use), rho_c,
     // and the flag bytes packed 8 bits per row into one 64-bit shift register
     using TRaw = typename TensorRaw<S>::type;
-    TRaw tD[D];
-    float rhoD[D];
-    uint64_t fD = 0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        tD[d] = TensorRaw<S>::identity();
-        rhoD[d] = 0.f;
+    constexpr bool RING = N >= 4;
+    RowConsts<TRaw, D, RING> K;
+    if constexpr (RING) {
+        __shared__ TRaw ringT[kWaves][D][kLanes];
+        __shared__ float ringR[kWaves][D][kLanes];
+        const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
+        K.t = ringT[wv];
+        K.rho = ringR[wv];
+        K.ln = int(threadIdx.x) & (kLanes - 1);
     }
+    K.init(TensorRaw<S>::identity());
+    uint64_t fD = 0;
     auto flag = [&](int d) { return unsigned(fD >> (8 * d)) & 0xffu; };
     // carried step-size bases of rows r - d (primal of u and v, dual of p),
     // and the step-size part of the row above the entering row
@@ -727,7 +797,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
         const Row w = load_row<TGV, false, S>(P, x, y0 - N, in_x);
         p_m1 = w.p;
         q_m1 = w.q;
-        tD[0] = TensorRaw<S>::pack(w.t);
+        K.set_first(TensorRaw<S>::pack(w.t));
         fD = w.f;
         above_steps(w.t, w.f, cy_up, my_up);
     }
@@ -748,13 +818,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
                 c = load_row<TGV, true, S>(P, x, r, in_x);
             }
         }
-#pragma unroll
-        for (int d = D - 1; d > 0; --d) {
-            tD[d] = tD[d - 1];
-            rhoD[d] = rhoD[d - 1];
-        }
-        tD[0] = TensorRaw<S>::pack(c.t);
-        rhoD[0] = c.rho;
+        K.push(TensorRaw<S>::pack(c.t), c.rho);
         fD = (fD << 8) | c.f;
         if constexpr (CB) {
 #pragma unroll
@@ -787,17 +851,18 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             const float2 v_in = i == 0 ? c.v : xv[i - 1][1];
             const float2 p_in = i == 0 ? c.p : yp[i - 1][0];
             const float4 q_in = i == 0 ? c.q : yq[i - 1][0];
-            const float4 t_ab = TensorRaw<S>::unpack(tD[2 * i + 1]);
+            const float4 t_ab = TensorRaw<S>::unpack(K.tens(2 * i + 1));
             const Above ab = i == 0 ? above_of(p_m1, q_m1, t_ab, flag(1))
                                     : above_of(yp[i - 1][1], yq[i - 1][1], t_ab, flag(2 * i + 1));
             float un;
             float2 vn;
-            const float4 t_q = i == 0 ? c.t : TensorRaw<S>::unpack(tD[2 * i]);
+            const float4 t_q = i == 0 ? c.t : TensorRaw<S>::unpack(K.tens(2 * i));
+            const float rho_q = i == 0 ? c.rho : K.rh(2 * i);
             if constexpr (CB)
-                primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[2 * i], flag(2 * i), ab, a0, a1, lam,
+                primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rho_q, flag(2 * i), ab, a0, a1, lam,
                                  tuD[2 * i] * a.tau_n[i], tvD[2 * i] * a.tau_n[i], un, vn);
             else
-                primal_at<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[2 * i], flag(2 * i), ab, a0, a1, lam, a.tau_n[i],
+                primal_at<TGV>(u_in, v_in, p_in, q_in, t_q, rho_q, flag(2 * i), ab, a0, a1, lam, a.tau_n[i],
                                un, vn);
             const float th = a.theta_n[i];
             const float ubn = un + th * (un - u_in);

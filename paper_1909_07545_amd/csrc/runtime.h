@@ -106,9 +106,9 @@ Sched schedule(const vfs_params& p);
 // which ev0 / ev1 (if given) bracket.
 int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // Iterations per pass (2, 3 or 4) of the dominant primal-dual launches for
-// pairs of level-0 geometry g (independent of the batch), or `requested` if
-// that is 2, 3 or 4.
-int pd_pass_iters(const Geometry& g, int requested);
+// pairs of level-0 geometry g in storage mode `storage` (independent of the
+// batch), or `requested` if that is 2, 3 or 4.
+int pd_pass_iters(const Geometry& g, int requested, int storage);
 // Parity change of the state copies (u/v, p/q) over run_pd's K iterations
 // with NP iterations per pass.
 void pd_parity(int K, int NP, int& pu, int& pp);

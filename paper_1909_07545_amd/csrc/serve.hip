@@ -299,7 +299,7 @@ vfs_status make_bucket(vfs_server* sv, const Geometry& g, Bucket*& out)
     CtrlBlock cb{};
     launch_write_ctrl(cb, kMaxBatch, b->ctrl_dev, b->stream);
     // parity change of one tick (the launch sequence of every tick, any size)
-    pd_parity(sv->params.iters, pd_pass_iters(b->g, sv->params.pass_iters), b->par_u, b->par_p);
+    pd_parity(sv->params.iters, pd_pass_iters(b->g, sv->params.pass_iters, sv->params.storage), b->par_u, b->par_p);
     if (sv->cfg.use_graphs) {
         prepare_pd();
         for (int gl = 0; gl < g.L; ++gl)
