@@ -182,6 +182,8 @@ def main():
         achieved_li = valu * 64 / avg_launch_s / 1e12
         alu = {"bound": "alu", "achieved": round(achieved_li, 2), "peak": round(peak_li, 2),
                "unit": "T lane-instructions/s", "frac": round(achieved_li / peak_li, 4),
+               "model": "every wave64 vector instruction holds a 16-lane SIMD for 4 cycles; a fraction above 1 "
+                        "means part of the mix issues in fewer cycles (the pass is then issue-bound)",
                "valu_wave64_per_launch": valu,
                "source": f"profiles/pdn{iters_per_launch}_kernel_batch2048_valu.json"}
 
@@ -212,7 +214,7 @@ def main():
         # copy measured on this GPU) or vector issue, whichever is closer to its peak
         hbm_near = roofline["counters_GBs"] / BEST_COPY_GBS if roofline["counters_GBs"] else None
         roofline["binding"] = ("vector issue" if hbm_near is None or alu["frac"] > hbm_near else "hbm") + \
-            f" (vector issue at {alu['frac']:.2f} of peak" + \
+            f" (vector issue at {alu['frac']:.2f} of the 4-cycle model's peak" + \
             (f", HBM traffic at {hbm_near:.2f} of the best copy measured, {BEST_COPY_GBS:.0f} GB/s)" if hbm_near
              else ")")
 
