@@ -115,7 +115,7 @@ vfs_status vfs_params_default(vfs_params* out);
 
 /* Rig set-up, once per calibration and resolution (Sec. III-B, Sec. IV-A,
  * Sec. IV-B).  cam0 and cam1 (host) must have equal width and height, both
- * divisible by 2^(levels-1); R (host, 9 doubles, row-major) and t (host, 3
+ * divisible by 2^(levels-1), width at most 2^20; R (host, 9 doubles, row-major) and t (host, 3
  * doubles) give X1 = R X0 + t.  Computes in double precision on the device,
  * for every level l: the trajectory field gamma'_l (unit tangents of the
  * epipolar curves of the pre-rotated pair, by projecting the unit sphere
@@ -303,7 +303,7 @@ vfs_status vfs_step_linearise(int width, int height, size_t pitch, const float* 
  * their scratch hold params->storage's values: float32 (2, 4, 4 per pixel),
  * or IEEE half / bfloat16 (2, 4, 4 16-bit values per pixel), rounded each
  * time a launch stores them; u, v, rho stay float32.  TV mode ignores v, q
- * and their scratch (may be NULL). */
+ * and their scratch (may be NULL).  width at most 2^20 (VFS_E_INVALID). */
 vfs_status vfs_step_pd(int width, int height, size_t pitch, const void* tpack, const float* rho,
                        const uint8_t* flags, float* u, float* v, void* p, void* q, float* scratch_u,
                        float* scratch_v, void* scratch_p, void* scratch_q, const vfs_params* params,

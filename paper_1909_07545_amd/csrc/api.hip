@@ -59,6 +59,7 @@ vfs_status check_camera(const vfs_camera* c, const char* name)
     if (!c) return fail(VFS_E_INVALID, "%s is NULL", name);
     if (c->width <= 0 || c->height <= 0 || !(c->fx > 0.0) || !(c->fy > 0.0))
         return fail(VFS_E_INVALID, "%s: bad size or focal length", name);
+    if (c->width > kMaxWidth) return fail(VFS_E_INVALID, "%s: width above %d", name, kMaxWidth);
     if (c->model < VFS_PINHOLE || c->model > VFS_ENHANCED_UNIFIED) return fail(VFS_E_INVALID, "%s: bad model", name);
     if (c->model == VFS_UNIFIED && !(c->k[0] >= 0.0)) return fail(VFS_E_INVALID, "%s: unified model needs xi >= 0", name);
     if (c->model == VFS_ENHANCED_UNIFIED && !(c->k[0] >= 0.0 && c->k[0] <= 1.0 && c->k[1] > 0.0))
@@ -949,8 +950,8 @@ vfs_status vfs_step_pd(int W, int H, size_t pitch, const void* tpack, const floa
     vfs_status st = check_params(params);
     if (st) return st;
     const bool tgv = params->reg == VFS_TGV;
-    if (W <= 0 || H <= 0 || pitch < size_t(W) || !tpack || !rho || !flags || !u || !p || !su || !sp || iters < 0 ||
-        (tgv && (!v || !q || !sv || !sq)))
+    if (W <= 0 || H <= 0 || W > kMaxWidth || pitch < size_t(W) || !tpack || !rho || !flags || !u || !p || !su || !sp ||
+        iters < 0 || (tgv && (!v || !q || !sv || !sq)))
         return fail(VFS_E_INVALID, "bad argument");
     if (iters == 0) return VFS_OK;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);

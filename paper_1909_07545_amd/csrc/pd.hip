@@ -68,6 +68,12 @@ constexpr int kBY = 16;
 // (measured on 8 pairs of 2048x2048: 552 us per launch at 16 rows, 517 at
 // 28, 520 at 36; FP32 is slower beyond 16: 677, 685 at 22, 693 at 28).
 constexpr int kBY16 = 28;
+// The FP32 four-iteration kernel is issue-bound too: its marches aim at 32
+// rows (measured on 8 pairs of 2048x2048: 817 us per launch at a 16-row
+// target, 779 at 24, 770 at 32 -- 30-row marches in five rounds; a target
+// that leaves fewer than kRoundsForShort rounds falls back to one round of
+// long marches, 801 us).
+constexpr int kBY4 = 32;
 constexpr int kBYs = 4;
 constexpr long long kRoundsForShort = 4;
 constexpr int kXcds = 8;
@@ -147,23 +153,124 @@ __device__ inline bool planes_of(const PdArgs& a, int z, Planes& P)
     return true;
 }
 
-template <bool TGV, bool PRIMAL, int S>
-__device__ inline Row load_row(const Planes& P, int x, int r, bool in_x)
+// Row reads and writes through buffer resources: one resource per plane row
+// (uniform, in scalar registers) and the lane's byte offset in the row (a
+// 32-bit vector register, the same at every step), so a row access costs no
+// vector address arithmetic.  A resource's record count is the row's width in
+// bytes, and the hardware returns zero for a read at or past it and drops
+// such a write: a lane left of the image (x < 0 wraps to an offset near 2^32)
+// or right of it reads zero, and a row outside the image (or one a march does
+// not need) is given a record count of 0 and reads zero -- the zero state of
+// the image's surroundings without moves or per-lane branches.  (The tensor
+// reads as 0 there, which only ever meets zero mask bits.)  Rows hold far
+// fewer than 2^25 columns, so every offset below stays under 2^32.
+constexpr int kRsrcWord3 = 0x00020000;   // untyped 32-bit data, no swizzle, no index
+// the column offset of a lane that writes nothing: times 4, 8 or 16 bytes it
+// is 2^29, 2^30 or 2^31, past any row's records
+constexpr uint32_t kNoColumn = 0x08000000u;
+
+__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void* plane, long long row, int pitch, int elem, int bytes)
 {
-    Row w = zero_row();
-    if (in_x && r >= 0 && r < P.H) {
-        const size_t o = (size_t)r * P.pitch + x;
-        w.u = P.u_in[o];
-        w.p = ld2<S>(P.p_in, o);
-        w.t = ld4<S>(P.tpack, o);
-        w.f = P.flags[o];
-        if (PRIMAL) w.rho = P.rho[o];
-        if (TGV) {
-            w.v = P.v_in[o];
-            w.q = ld4<S>(P.q_in, o);
-        }
+    char* base = const_cast<char*>(static_cast<const char*>(plane)) + row * pitch * elem;
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, kRsrcWord3);
+}
+
+template <int S> __device__ inline float2 dec2(uint32_t v)
+{
+    if constexpr (S == ST_F32) return make_float2(0.f, 0.f);
+    else return make_float2(dec16<S>(uint16_t(v & 0xffffu)), dec16<S>(uint16_t(v >> 16)));
+}
+
+template <int S> __device__ inline float4 dec4(uint32_t lo, uint32_t hi)
+{
+    if constexpr (S == ST_F32) return make_float4(0.f, 0.f, 0.f, 0.f);
+    else return make_float4(dec16<S>(uint16_t(lo & 0xffffu)), dec16<S>(uint16_t(lo >> 16)),
+                            dec16<S>(uint16_t(hi & 0xffffu)), dec16<S>(uint16_t(hi >> 16)));
+}
+
+template <int S> __device__ inline float2 rd2(__amdgpu_buffer_rsrc_t rs, uint32_t x)
+{
+    if constexpr (S == ST_F32) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, x * 8u, 0, 0);
+        return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+    } else {
+        return dec2<S>(__builtin_amdgcn_raw_buffer_load_b32(rs, x * 4u, 0, 0));
+    }
+}
+
+template <int S> __device__ inline float4 rd4(__amdgpu_buffer_rsrc_t rs, uint32_t x)
+{
+    if constexpr (S == ST_F32) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, x * 16u, 0, 0);
+        return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, x * 8u, 0, 0);
+        return dec4<S>(v[0], v[1]);
+    }
+}
+
+// Row r of the state planes at every lane (zero outside the image, and for
+// rows with valid = false).
+template <bool TGV, bool PRIMAL, int S>
+__device__ inline Row read_row(const Planes& P, int x, int r, bool valid = true)
+{
+    constexpr int E2 = S == ST_F32 ? 8 : 4, E4 = S == ST_F32 ? 16 : 8;
+    const bool ok = valid && r >= 0 && r < P.H;
+    const long long rr = ok ? r : 0;
+    const int W = ok ? P.W : 0;
+    const uint32_t xo = uint32_t(x);
+    Row w;
+    w.u = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(row_rsrc(P.u_in, rr, P.pitch, 4, W * 4), xo * 4u, 0, 0));
+    w.p = rd2<S>(row_rsrc(P.p_in, rr, P.pitch, E2, W * E2), xo);
+    w.t = rd4<S>(row_rsrc(P.tpack, rr, P.pitch, E4, W * E4), xo);
+    w.f = __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(P.flags, rr, P.pitch, 1, W), xo, 0, 0);
+    w.rho = 0.f;
+    if (PRIMAL)
+        w.rho = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(row_rsrc(P.rho, rr, P.pitch, 4, W * 4), xo * 4u,
+                                                                     0, 0));
+    w.v = make_float2(0.f, 0.f);
+    w.q = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (TGV) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(P.v_in, rr, P.pitch, 8, W * 8), xo * 8u, 0, 0);
+        w.v = make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+        w.q = rd4<S>(row_rsrc(P.q_in, rr, P.pitch, E4, W * E4), xo);
     }
     return w;
+}
+
+// Writes of row r's results by the owner lanes (xs: the lane's column, or
+// a column past any row for the other lanes).
+template <bool TGV>
+__device__ inline void write_primal(const Planes& P, uint32_t xs, int r, float un, float2 vn)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), row_rsrc(P.u_out, r, P.pitch, 4, P.W * 4), xs * 4u, 0, 0);
+    if (TGV) {
+        const __attribute__((ext_vector_type(2))) uint32_t v = {__float_as_uint(vn.x), __float_as_uint(vn.y)};
+        __builtin_amdgcn_raw_buffer_store_b64(v, row_rsrc(P.v_out, r, P.pitch, 8, P.W * 8), xs * 8u, 0, 0);
+    }
+}
+
+template <bool TGV, int S>
+__device__ inline void write_dual(const Planes& P, uint32_t xs, int r, float2 pn, float4 qn)
+{
+    if constexpr (S == ST_F32) {
+        const __attribute__((ext_vector_type(2))) uint32_t pv = {__float_as_uint(pn.x), __float_as_uint(pn.y)};
+        __builtin_amdgcn_raw_buffer_store_b64(pv, row_rsrc(P.p_out, r, P.pitch, 8, P.W * 8), xs * 8u, 0, 0);
+        if (TGV) {
+            const __attribute__((ext_vector_type(4))) uint32_t qv = {__float_as_uint(qn.x), __float_as_uint(qn.y),
+                                                                     __float_as_uint(qn.z), __float_as_uint(qn.w)};
+            __builtin_amdgcn_raw_buffer_store_b128(qv, row_rsrc(P.q_out, r, P.pitch, 16, P.W * 16), xs * 16u, 0, 0);
+        }
+    } else {
+        const uint32_t pv = uint32_t(enc16<S>(pn.x)) | (uint32_t(enc16<S>(pn.y)) << 16);
+        __builtin_amdgcn_raw_buffer_store_b32(pv, row_rsrc(P.p_out, r, P.pitch, 4, P.W * 4), xs * 4u, 0, 0);
+        if (TGV) {
+            const __attribute__((ext_vector_type(2))) uint32_t qv = {
+                uint32_t(enc16<S>(qn.x)) | (uint32_t(enc16<S>(qn.y)) << 16),
+                uint32_t(enc16<S>(qn.z)) | (uint32_t(enc16<S>(qn.w)) << 16)};
+            __builtin_amdgcn_raw_buffer_store_b64(qv, row_rsrc(P.q_out, r, P.pitch, 8, P.W * 8), xs * 8u, 0, 0);
+        }
+    }
 }
 
 // A flag bit as the float 0 or 1 that multiplies a masked difference: a
@@ -383,8 +490,8 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a, int by, i
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int x = tx * kCols - 1 + lane;
-    const bool in_x = x >= 0 && x < P.W;
-    const bool owner = lane >= 1 && lane <= kCols && in_x;
+    const bool owner = lane >= 1 && lane <= kCols && x < P.W;
+    const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
     const int y0 = tk.y0;
     if (y0 >= P.H) return;
     const int y1 = min(y0 + by, P.H);           // owned rows [y0, y1)
@@ -399,7 +506,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a, int by, i
     float2 vb_prev = make_float2(0.f, 0.f);
     Above ab = {0.f, 0.f, 0.f, 0.f, 0.f};
     if (PRIMAL) {
-        const Row w = load_row<TGV, false, S>(P, x, y0 - 1, in_x);
+        const Row w = read_row<TGV, false, S>(P, x, y0 - 1);
         ab = above_of(w.p, w.q, w.t, w.f);
     }
 
@@ -409,25 +516,21 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a, int by, i
     // kernels weigh this against occupancy, see below)
     constexpr bool PF = true;
     Row nxt = zero_row();
-    if constexpr (PF) nxt = load_row<TGV, PRIMAL, S>(P, x, y0, in_x);
+    if constexpr (PF) nxt = read_row<TGV, PRIMAL, S>(P, x, y0);
     for (int r = y0; r <= r_end; ++r) {
         Row c;
         if constexpr (PF) {
             c = nxt;
-            if (r + 1 <= r_end) nxt = load_row<TGV, PRIMAL, S>(P, x, r + 1, in_x);
+            if (r + 1 <= r_end) nxt = read_row<TGV, PRIMAL, S>(P, x, r + 1);
         } else {
-            c = load_row<TGV, PRIMAL, S>(P, x, r, in_x);
+            c = read_row<TGV, PRIMAL, S>(P, x, r);
         }
         // primal step at row r: x^k from x^{k-1} and y^k
         float un = c.u;
         float2 vn = c.v;
         if (PRIMAL) {
             primal_at<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab, a0, a1, a.lambda, a.tau_scale, un, vn);
-            if (owner && r < y1) {
-                const size_t o = (size_t)r * P.pitch + x;
-                P.u_out[o] = un;
-                if (TGV) P.v_out[o] = vn;
-            }
+            if (r < y1) write_primal<TGV>(P, xs, r, un, vn);
         }
         // over-relaxation (xbar stays in registers)
         const float ub = un + a.theta * (un - c.u);
@@ -436,14 +539,12 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a, int by, i
         if (DUAL) {
             const float ub_r = from_right(ub_prev);
             const float2 vb_r = make_float2(from_right(vb_prev.x), from_right(vb_prev.y));
-            if (r > y0 && owner) {
+            if (r > y0) {
                 float2 pn;
                 float4 qn;
                 dual_at<TGV>(p_prev, q_prev, t_prev, f_prev, ub_prev, vb_prev, ub_r, vb_r, ub, vb, a0, a1,
                              a.sigma_scale, sq1, pn, qn);
-                const size_t o = (size_t)(r - 1) * P.pitch + x;
-                st2<S>(P.p_out, o, pn);
-                if (TGV) st4<S>(P.q_out, o, qn);
+                write_dual<TGV, S>(P, xs, r - 1, pn, qn);
             }
         }
         // slide the window
@@ -477,8 +578,8 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int x = tx * kCols2 - 2 + lane;
-    const bool in_x = x >= 0 && x < P.W;
-    const bool owner = lane >= 2 && lane <= kCols2 + 1 && in_x;
+    const bool owner = lane >= 2 && lane <= kCols2 + 1 && x < P.W;
+    const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
     const int y0 = tk.y0;
     if (y0 >= P.H) return;
     const int y1 = min(y0 + by, P.H);
@@ -488,7 +589,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
     // iteration 1: "above" of row r-1, and row r-1 as B needs it
     Above ab1;
     {
-        const Row w = load_row<TGV, false, S>(P, x, y0 - 2, in_x);
+        const Row w = read_row<TGV, false, S>(P, x, y0 - 2);
         ab1 = above_of(w.p, w.q, w.t, w.f);
     }
     float2 p_m1 = make_float2(0.f, 0.f);
@@ -517,7 +618,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
     // rows are loaded one step ahead of their use (see pd_kernel)
     constexpr bool PF = true;
     Row nxt = zero_row();
-    if constexpr (PF) nxt = load_row<TGV, true, S>(P, x, y0 - 1, in_x);
+    if constexpr (PF) nxt = read_row<TGV, true, S>(P, x, y0 - 1);
     for (int r = y0 - 1; r <= y1 + 2; ++r) {
         // A: iteration-1 primal at row r
         Row c = zero_row();
@@ -526,9 +627,9 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
         if (r <= y1 + 1) {
             if constexpr (PF) {
                 c = nxt;
-                if (r + 1 <= y1 + 1) nxt = load_row<TGV, true, S>(P, x, r + 1, in_x);
+                if (r + 1 <= y1 + 1) nxt = read_row<TGV, true, S>(P, x, r + 1);
             } else {
-                c = load_row<TGV, true, S>(P, x, r, in_x);
+                c = read_row<TGV, true, S>(P, x, r);
             }
             if constexpr (TGV) {
                 const PrimalBases b = primal_bases<TGV>(c.t, c.f, ab1.cy, ab1.my, a0, a1);
@@ -570,11 +671,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
                                un2, vn2);
             ub2 = un2 + a.theta2 * (un2 - un1_m2);
             vb2 = make_float2(vn2.x + a.theta2 * (vn2.x - vn1_m2.x), vn2.y + a.theta2 * (vn2.y - vn1_m2.y));
-            if (owner && r - 2 < y1) {
-                const size_t o = (size_t)(r - 2) * P.pitch + x;
-                P.u_out[o] = un2;
-                if (TGV) P.v_out[o] = vn2;
-            }
+            if (r - 2 < y1) write_primal<TGV>(P, xs, r - 2, un2, vn2);
         }
         // D: iteration-2 dual at row r-3 -> y^{k+2}(r-3)
         if (r >= y0 + 3) {
@@ -588,11 +685,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
             else
                 dual_at<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1,
                              a.sigma_scale2, sq2, pn, qn);
-            if (owner) {
-                const size_t o = (size_t)(r - 3) * P.pitch + x;
-                st2<S>(P.p_out, o, pn);
-                if (TGV) st4<S>(P.q_out, o, qn);
-            }
+            write_dual<TGV, S>(P, xs, r - 3, pn, qn);
         }
         // slide the windows (deepest first)
         tu_m2 = tu_m1;
@@ -740,7 +833,7 @@ template <bool TGV, int S, int N> constexpr bool kCarryBases = TGV && N == 3;
 // Downward march: at step r, iteration i takes its primal step at row r - 2i
 // and its dual step at row r - 2i - 1 (the dual needs xbar of the row below).
 template <bool TGV, int S, int N>
-__device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int x, bool in_x, bool owner, int y0,
+__device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int x, bool owner, int y0,
                                            int y1)
 {
     constexpr int D = 2 * N;    // depth of the constants' delay line
@@ -794,7 +887,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
     float2 p_m1;
     float4 q_m1;
     {
-        const Row w = load_row<TGV, false, S>(P, x, y0 - N, in_x);
+        const Row w = read_row<TGV, false, S>(P, x, y0 - N);
         p_m1 = w.p;
         q_m1 = w.q;
         K.set_first(TensorRaw<S>::pack(w.t));
@@ -805,19 +898,9 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
     // no prefetch here: its registers would cost a wavefront per SIMD, which
     // is worth more on the bandwidth-bound grids this kernel serves
     // (measured)
-    constexpr bool PF = false;
-    Row nxt = zero_row();
-    if constexpr (PF) nxt = load_row<TGV, true, S>(P, x, r_lo, in_x);
+    const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
     for (int r = r_lo; r <= r_hi; ++r) {
-        Row c = zero_row();
-        if (r <= r_load) {
-            if constexpr (PF) {
-                c = nxt;
-                if (r + 1 <= r_load) nxt = load_row<TGV, true, S>(P, x, r + 1, in_x);
-            } else {
-                c = load_row<TGV, true, S>(P, x, r, in_x);
-            }
-        }
+        const Row c = read_row<TGV, true, S>(P, x, r, r <= r_load);
         K.push(TensorRaw<S>::pack(c.t), c.rho);
         fD = (fD << 8) | c.f;
         if constexpr (CB) {
@@ -867,11 +950,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             const float th = a.theta_n[i];
             const float ubn = un + th * (un - u_in);
             const float2 vbn = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
-            if (i == N - 1 && owner && pr >= y0 && pr < y1) {
-                const size_t o = (size_t)pr * P.pitch + x;
-                P.u_out[o] = un;
-                if (TGV) P.v_out[o] = vn;
-            }
+            if (i == N - 1 && pr >= y0 && pr < y1) write_primal<TGV>(P, xs, pr, un, vn);
             // dual step of iteration i at row r - 2i - 1 (inside its rows
             // whenever the row below is, save the first)
             const int dr = pr - 1;
@@ -888,11 +967,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
                 else
                     dual_at<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, ubn, vbn, a0, a1,
                                  a.sigma_n[i], sqn[i], pn, qn);
-                if (i == N - 1 && owner && dr >= y0 && dr < y1) {
-                    const size_t o = (size_t)dr * P.pitch + x;
-                    st2<S>(P.p_out, o, pn);
-                    if (TGV) st4<S>(P.q_out, o, qn);
-                }
+                if (i == N - 1 && dr >= y0 && dr < y1) write_dual<TGV, S>(P, xs, dr, pn, qn);
                 yp[i][1] = yp[i][0];
                 yp[i][0] = pn;
                 yq[i][1] = yq[i][0];
@@ -917,7 +992,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
 // Iteration i covers the same rows as in the downward march, so every value
 // is computed from the same inputs.
 template <bool TGV, int S, int N>
-__device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x, bool in_x, bool owner, int y0,
+__device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x, bool owner, int y0,
                                          int y1)
 {
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
@@ -955,10 +1030,11 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
         yq[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     const int r_hi = y1 + N - 1, r_lo = y0 - (N - 1);
-    Row c = load_row<TGV, true, S>(P, x, r_hi, in_x);
+    const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
+    Row c = read_row<TGV, true, S>(P, x, r_hi);
     for (int r = r_hi; r >= r_lo; --r) {
         // the row above: iteration 0's y^k there, and the next step's row
-        const Row nx = load_row<TGV, true, S>(P, x, r - 1, in_x);
+        const Row nx = read_row<TGV, true, S>(P, x, r - 1);
 #pragma unroll
         for (int d = N - 1; d > 0; --d) {
             tD[d] = tD[d - 1];
@@ -1014,11 +1090,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
                 xnv[i] = vn;
                 xbnu[i] = un + th * (un - u_in);
                 xbnv[i] = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
-                if (i == N - 1 && owner && q >= y0 && q < y1) {
-                    const size_t o = (size_t)q * P.pitch + x;
-                    P.u_out[o] = un;
-                    if (TGV) P.v_out[o] = vn;
-                }
+                if (i == N - 1 && q >= y0 && q < y1) write_primal<TGV>(P, xs, q, un, vn);
             }
             ynp[i] = make_float2(0.f, 0.f);
             ynq[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1031,11 +1103,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
                 else
                     dual_at<TGV>(p_in, q_in, t_q, flag(i), xbnu[i], xbnv[i], ub_r, vb_r, xbu[i], xbv[i], a0, a1,
                                  a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
-                if (i == N - 1 && owner && q >= y0 && q < y1) {
-                    const size_t o = (size_t)q * P.pitch + x;
-                    st2<S>(P.p_out, o, ynp[i]);
-                    if (TGV) st4<S>(P.q_out, o, ynq[i]);
-                }
+                if (i == N - 1 && q >= y0 && q < y1) write_dual<TGV, S>(P, xs, q, ynp[i], ynq[i]);
             }
         }
 #pragma unroll
@@ -1058,7 +1126,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
 // on the same inputs, so each pixel's result does not depend on the
 // direction (this file contracts multiply-adds only within one expression).
 template <bool TGV, int S, int N>
-__global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) void pdn_kernel(PdArgs a, int by,
+__global__ __launch_bounds__(kLanes * kWaves, (N == 4 || S != ST_F32) ? 4 : 1) void pdn_kernel(PdArgs a, int by,
                                                                                                int segs)
 {
     constexpr int kColsN = kLanes - 2 * N;
@@ -1071,15 +1139,14 @@ __global__ __launch_bounds__(kLanes * kWaves, (S != ST_F32 && N == 3) ? 4 : 1) v
 
     const int lane = threadIdx.x & (kLanes - 1);
     const int x = tx * kColsN - N + lane;
-    const bool in_x = x >= 0 && x < P.W;
-    const bool owner = lane >= N && lane < N + kColsN && in_x;
+    const bool owner = lane >= N && lane < N + kColsN && x < P.W;
     const int y0 = tk.y0;
     if (y0 >= P.H) return;
     const int y1 = min(y0 + by, P.H);
     if ((y0 / by) & 1)
-        march_up<TGV, S, N>(a, P, x, in_x, owner, y0, y1);
+        march_up<TGV, S, N>(a, P, x, owner, y0, y1);
     else
-        march_down<TGV, S, N>(a, P, x, in_x, owner, y0, y1);
+        march_down<TGV, S, N>(a, P, x, owner, y0, y1);
 }
 
 // Wavefronts of a kernel that the current device holds at once (its
@@ -1191,7 +1258,7 @@ template <bool TGV, int S, int N>
 void launch_fusedn(const PdArgs& a, hipStream_t s)
 {
     const March m = march_shape(a, kLanes - 2 * N, pdn_kernel<TGV, S, N>, short_march_floor(a, kLanes - 2 * N),
-                                S == ST_F32 ? kBY : kBY16);
+                                S == ST_F32 ? (N == 4 ? kBY4 : kBY) : kBY16);
     if (m.blocks)
         hipLaunchKernelGGL((pdn_kernel<TGV, S, N>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }

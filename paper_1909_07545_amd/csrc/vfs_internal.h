@@ -19,6 +19,10 @@ enum : uint8_t {
 
 constexpr int kMaxLevels = 12;
 constexpr int kMaxBatch = 32;
+// Widest image row in pixels: the primal-dual kernels address a row through a
+// buffer resource with 32-bit byte offsets and record counts (16 bytes per
+// pixel at most).
+constexpr int kMaxWidth = 1 << 20;
 
 // ----------------------------------------------------------------- camera
 // Radially symmetric models: a ray at angle theta from the axis lands at
