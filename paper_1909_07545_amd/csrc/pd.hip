@@ -830,11 +830,18 @@ template <typename TRaw, int D> struct RowConsts<TRaw, D, true> {
 // 16-bit 118); the four-iteration kernels would drop one.
 template <bool TGV, int S, int N> constexpr bool kCarryBases = TGV && N == 3;
 
+// A step's parity as a type: the marches run two steps per loop trip, so
+// that the slot of a two-step window that a step reads or writes is a
+// constant and the windows slide without register moves.
+template <int V> struct Par {
+    static constexpr int v = V;
+};
+
 // Downward march: at step r, iteration i takes its primal step at row r - 2i
 // and its dual step at row r - 2i - 1 (the dual needs xbar of the row below).
 template <bool TGV, int S, int N>
-__device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int x, bool owner, int y0,
-                                           int y1)
+__device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int x, bool owner, int y0, int y1,
+                                           typename TensorRaw<S>::type (*ringT)[kLanes], float (*ringR)[kLanes])
 {
     constexpr int D = 2 * N;    // depth of the constants' delay line
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
@@ -849,11 +856,8 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
     constexpr bool RING = N >= 4;
     RowConsts<TRaw, D, RING> K;
     if constexpr (RING) {
-        __shared__ TRaw ringT[kWaves][D][kLanes];
-        __shared__ float ringR[kWaves][D][kLanes];
-        const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
-        K.t = ringT[wv];
-        K.rho = ringR[wv];
+        K.t = ringT;
+        K.rho = ringR;
         K.ln = int(threadIdx.x) & (kLanes - 1);
     }
     K.init(TensorRaw<S>::identity());
@@ -866,8 +870,11 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
     float cy_up = 0.f, my_up = 0.f;
 #pragma unroll
     for (int d = 0; d < D; ++d) tuD[d] = tvD[d] = sgD[d] = 0.f;
-    // per iteration i: its primal outputs x of the last two steps, its xbar
-    // of the last step, its dual outputs y of the last two steps
+    // per iteration i: its primal outputs x and dual outputs y of the last
+    // two steps, in slots by the parity of the step that wrote them (a step
+    // of parity s finds the previous step's values in slot s ^ 1 and the
+    // ones before in slot s, then writes slot s), and its xbar of the last
+    // step
     float xu[N][2], xbu[N];
     float2 xv[N][2], xbv[N], yp[N][2];
     float4 yq[N][2];
@@ -883,23 +890,26 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             yq[i][k] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
     }
-    // y^k of the row above the current one (from memory), for iteration 0
-    float2 p_m1;
-    float4 q_m1;
+    // y^k of the rows of the last two steps (from memory) for iteration 0, in
+    // the same slots; the row above the first step (which has parity 0)
+    float2 pm[2];
+    float4 qm[2];
+    pm[0] = make_float2(0.f, 0.f);
+    qm[0] = make_float4(0.f, 0.f, 0.f, 0.f);
     {
         const Row w = read_row<TGV, false, S>(P, x, y0 - N);
-        p_m1 = w.p;
-        q_m1 = w.q;
+        pm[1] = w.p;
+        qm[1] = w.q;
         K.set_first(TensorRaw<S>::pack(w.t));
         fD = w.f;
         above_steps(w.t, w.f, cy_up, my_up);
     }
     const int r_lo = y0 - (N - 1), r_hi = y1 + 2 * N - 2, r_load = y1 + N - 1;
-    // no prefetch here: its registers would cost a wavefront per SIMD, which
-    // is worth more on the bandwidth-bound grids this kernel serves
-    // (measured)
     const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
-    for (int r = r_lo; r <= r_hi; ++r) {
+    // no prefetch of the next row: its registers would cost a wavefront per
+    // SIMD, which is worth more here (measured)
+    auto step = [&](const int r, auto par) {
+        constexpr int s = decltype(par)::v, o = s ^ 1;
         const Row c = read_row<TGV, true, S>(P, x, r, r <= r_load);
         K.push(TensorRaw<S>::pack(c.t), c.rho);
         fD = (fD << 8) | c.f;
@@ -919,10 +929,10 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
 
         // Later iterations first: iteration i reads iteration i - 1's
         // windows as they stood after the previous step.  An iteration
-        // updates its windows only at steps inside its rows; it is inside
+        // writes its windows only at steps inside its rows; it is inside
         // them at the two steps before any step at which iteration i + 1
-        // (or its own dual) reads them, so every read sees the same values
-        // as with a shift at every step.
+        // (or its own dual) reads them, so every read sees the value of the
+        // step it means.
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const int i = N - 1 - k;
@@ -930,13 +940,13 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             // primal step of iteration i at row r - 2i
             const int pr = r - 2 * i;
             if (pr < lo || pr > hi) continue;
-            const float u_in = i == 0 ? c.u : xu[i - 1][1];
-            const float2 v_in = i == 0 ? c.v : xv[i - 1][1];
-            const float2 p_in = i == 0 ? c.p : yp[i - 1][0];
-            const float4 q_in = i == 0 ? c.q : yq[i - 1][0];
+            const float u_in = i == 0 ? c.u : xu[i - 1][s];
+            const float2 v_in = i == 0 ? c.v : xv[i - 1][s];
+            const float2 p_in = i == 0 ? c.p : yp[i - 1][o];
+            const float4 q_in = i == 0 ? c.q : yq[i - 1][o];
             const float4 t_ab = TensorRaw<S>::unpack(K.tens(2 * i + 1));
-            const Above ab = i == 0 ? above_of(p_m1, q_m1, t_ab, flag(1))
-                                    : above_of(yp[i - 1][1], yq[i - 1][1], t_ab, flag(2 * i + 1));
+            const Above ab = i == 0 ? above_of(pm[o], qm[o], t_ab, flag(1))
+                                    : above_of(yp[i - 1][s], yq[i - 1][s], t_ab, flag(2 * i + 1));
             float un;
             float2 vn;
             const float4 t_q = i == 0 ? c.t : TensorRaw<S>::unpack(K.tens(2 * i));
@@ -955,8 +965,8 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             // whenever the row below is, save the first)
             const int dr = pr - 1;
             if (dr >= lo) {
-                const float2 py = i == 0 ? p_m1 : yp[i - 1][1];
-                const float4 qy = i == 0 ? q_m1 : yq[i - 1][1];
+                const float2 py = i == 0 ? pm[o] : yp[i - 1][s];
+                const float4 qy = i == 0 ? qm[o] : yq[i - 1][s];
                 const float ub_r = from_right(xbu[i]);
                 const float2 vb_r = make_float2(from_right(xbv[i].x), from_right(xbv[i].y));
                 float2 pn;
@@ -968,20 +978,24 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
                     dual_at<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, ubn, vbn, a0, a1,
                                  a.sigma_n[i], sqn[i], pn, qn);
                 if (i == N - 1 && dr >= y0 && dr < y1) write_dual<TGV, S>(P, xs, dr, pn, qn);
-                yp[i][1] = yp[i][0];
-                yp[i][0] = pn;
-                yq[i][1] = yq[i][0];
-                yq[i][0] = qn;
+                yp[i][s] = pn;
+                yq[i][s] = qn;
             }
-            xu[i][1] = xu[i][0];
-            xu[i][0] = un;
-            xv[i][1] = xv[i][0];
-            xv[i][0] = vn;
+            xu[i][s] = un;
+            xv[i][s] = vn;
             xbu[i] = ubn;
             xbv[i] = vbn;
         }
-        p_m1 = c.p;
-        q_m1 = c.q;
+        pm[s] = c.p;
+        qm[s] = c.q;
+    };
+    for (int r = r_lo; r <= r_hi; r += 2) {
+        step(r, Par<0>());
+        // keep the two steps apart: interleaved, they would need more
+        // registers than four wavefronts per SIMD leave
+        __builtin_amdgcn_sched_barrier(0);
+        if (r + 1 <= r_hi) step(r + 1, Par<1>());
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -992,56 +1006,58 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
 // Iteration i covers the same rows as in the downward march, so every value
 // is computed from the same inputs.
 template <bool TGV, int S, int N>
-__device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x, bool owner, int y0,
-                                         int y1)
+__device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x, bool owner, int y0, int y1,
+                                         typename TensorRaw<S>::type (*ringT)[kLanes], float (*ringR)[kLanes])
 {
     const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
     float sqn[N];   // the steps of q, once per march
 #pragma unroll
     for (int i = 0; i < N; ++i) sqn[i] = a.sigma_n[i] / (2.f * a0);
-    // constants of rows r + d (d = 0 .. N-1) after the shift of step r
+    // constants of rows r + d (d = 0 .. N-1) after the push of step r (in
+    // the four-iteration kernels: N slots of the LDS ring of march_down)
     using TRaw = typename TensorRaw<S>::type;
-    TRaw tD[N];
-    float rhoD[N];
-    uint64_t fD = 0;
-#pragma unroll
-    for (int d = 0; d < N; ++d) {
-        tD[d] = TensorRaw<S>::identity();
-        rhoD[d] = 0.f;
+    constexpr bool RING = N >= 4;
+    RowConsts<TRaw, N, RING> K;
+    if constexpr (RING) {
+        K.t = ringT;
+        K.rho = ringR;
+        K.ln = int(threadIdx.x) & (kLanes - 1);
     }
+    K.init(TensorRaw<S>::identity());
+    uint64_t fD = 0;
     auto flag = [&](int d) { return unsigned(fD >> (8 * d)) & 0xffu; };
     // carried step-size bases of rows r + d (primal of u and v, dual of p)
     constexpr bool CB = kCarryBases<TGV, S, N>;
     float tuD[N], tvD[N], sgD[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) tuD[d] = tvD[d] = sgD[d] = 0.f;
-    // per iteration i, from its previous step (row r + 1 + i): primal output,
-    // xbar and dual output
-    float xu[N], xbu[N];
-    float2 xv[N], xbv[N], yp[N];
-    float4 yq[N];
+    // per iteration i: primal output, xbar and dual output of the previous
+    // step (row r + 1 + i) in slot s ^ 1 and of the current step in slot s
+    float xu[N][2], xbu[N][2];
+    float2 xv[N][2], xbv[N][2], yp[N][2];
+    float4 yq[N][2];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        xu[i] = 0.f;
-        xbu[i] = 0.f;
-        xv[i] = make_float2(0.f, 0.f);
-        xbv[i] = make_float2(0.f, 0.f);
-        yp[i] = make_float2(0.f, 0.f);
-        yq[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            xu[i][k] = 0.f;
+            xbu[i][k] = 0.f;
+            xv[i][k] = make_float2(0.f, 0.f);
+            xbv[i][k] = make_float2(0.f, 0.f);
+            yp[i][k] = make_float2(0.f, 0.f);
+            yq[i][k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
     }
     const int r_hi = y1 + N - 1, r_lo = y0 - (N - 1);
     const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
+    // the current row (rows in two slots instead, the registers exceed what
+    // four wavefronts per SIMD leave)
     Row c = read_row<TGV, true, S>(P, x, r_hi);
-    for (int r = r_hi; r >= r_lo; --r) {
+    auto step = [&](const int r, auto par) {
+        constexpr int s = decltype(par)::v, o = s ^ 1;
         // the row above: iteration 0's y^k there, and the next step's row
         const Row nx = read_row<TGV, true, S>(P, x, r - 1);
-#pragma unroll
-        for (int d = N - 1; d > 0; --d) {
-            tD[d] = tD[d - 1];
-            rhoD[d] = rhoD[d - 1];
-        }
-        tD[0] = TensorRaw<S>::pack(c.t);
-        rhoD[0] = c.rho;
+        K.push(TensorRaw<S>::pack(c.t), c.rho);
         fD = (fD << 8) | c.f;
         if constexpr (CB) {
 #pragma unroll
@@ -1058,64 +1074,62 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
             sgD[0] = dual_base<TGV>(c.t, c.f, a1);
         }
 
-        float xnu[N], xbnu[N];
-        float2 xnv[N], xbnv[N], ynp[N];
-        float4 ynq[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const int lo = y0 - (N - 1 - i), hi = y1 + (N - 1 - i);
             const int q = r + i;
-            const float u_in = i == 0 ? c.u : xu[i - 1];
-            const float2 v_in = i == 0 ? c.v : xv[i - 1];
-            const float2 p_in = i == 0 ? c.p : yp[i - 1];
-            const float4 q_in = i == 0 ? c.q : yq[i - 1];
-            const float4 t_q = i == 0 ? c.t : TensorRaw<S>::unpack(tD[i]);
-            const Above ab = i == 0 ? above_of(nx.p, nx.q, nx.t, nx.f)
-                                    : above_of(ynp[i - 1], ynq[i - 1], TensorRaw<S>::unpack(tD[i - 1]), flag(i - 1));
-            xnu[i] = 0.f;
-            xnv[i] = make_float2(0.f, 0.f);
-            xbnu[i] = 0.f;
-            xbnv[i] = make_float2(0.f, 0.f);
+            const float u_in = i == 0 ? c.u : xu[i - 1][o];
+            const float2 v_in = i == 0 ? c.v : xv[i - 1][o];
+            const float2 p_in = i == 0 ? c.p : yp[i - 1][o];
+            const float4 q_in = i == 0 ? c.q : yq[i - 1][o];
+            const float4 t_q = i == 0 ? c.t : TensorRaw<S>::unpack(K.tens(i));
+            const float rho_q = i == 0 ? c.rho : K.rh(i);
+            // every slot s is written at every step (zero outside the
+            // iteration's rows), so what a step leaves in slot s ^ 1 is dead
+            // once the step has read it
+            float un = 0.f, ub = 0.f;
+            float2 vn = make_float2(0.f, 0.f), vb = make_float2(0.f, 0.f);
             if (q >= lo && q <= hi) {
-                float un;
-                float2 vn;
+                const Above ab = i == 0 ? above_of(nx.p, nx.q, nx.t, nx.f)
+                                        : above_of(yp[i - 1][s], yq[i - 1][s],
+                                                   i == 1 ? c.t : TensorRaw<S>::unpack(K.tens(i - 1)), flag(i - 1));
                 if constexpr (CB)
-                    primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[i], flag(i), ab, a0, a1, lam,
-                                     tuD[i] * a.tau_n[i], tvD[i] * a.tau_n[i], un, vn);
+                    primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rho_q, flag(i), ab, a0, a1, lam, tuD[i] * a.tau_n[i],
+                                     tvD[i] * a.tau_n[i], un, vn);
                 else
-                    primal_at<TGV>(u_in, v_in, p_in, q_in, t_q, rhoD[i], flag(i), ab, a0, a1, lam, a.tau_n[i], un,
-                                   vn);
+                    primal_at<TGV>(u_in, v_in, p_in, q_in, t_q, rho_q, flag(i), ab, a0, a1, lam, a.tau_n[i], un, vn);
                 const float th = a.theta_n[i];
-                xnu[i] = un;
-                xnv[i] = vn;
-                xbnu[i] = un + th * (un - u_in);
-                xbnv[i] = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
+                ub = un + th * (un - u_in);
+                vb = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
                 if (i == N - 1 && q >= y0 && q < y1) write_primal<TGV>(P, xs, q, un, vn);
             }
-            ynp[i] = make_float2(0.f, 0.f);
-            ynq[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            xu[i][s] = un;
+            xv[i][s] = vn;
+            xbu[i][s] = ub;
+            xbv[i][s] = vb;
+            float2 pn = make_float2(0.f, 0.f);
+            float4 qn = make_float4(0.f, 0.f, 0.f, 0.f);
             if (q >= lo && q <= hi - 1) {
-                const float ub_r = from_right(xbnu[i]);
-                const float2 vb_r = make_float2(from_right(xbnv[i].x), from_right(xbnv[i].y));
+                const float ub_r = from_right(ub);
+                const float2 vb_r = make_float2(from_right(vb.x), from_right(vb.y));
                 if constexpr (CB)
-                    dual_step<TGV>(p_in, q_in, t_q, flag(i), xbnu[i], xbnv[i], ub_r, vb_r, xbu[i], xbv[i], a0, a1,
-                                   sgD[i] * a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
+                    dual_step<TGV>(p_in, q_in, t_q, flag(i), ub, vb, ub_r, vb_r, xbu[i][o], xbv[i][o], a0, a1,
+                                   sgD[i] * a.sigma_n[i], sqn[i], pn, qn);
                 else
-                    dual_at<TGV>(p_in, q_in, t_q, flag(i), xbnu[i], xbnv[i], ub_r, vb_r, xbu[i], xbv[i], a0, a1,
-                                 a.sigma_n[i], sqn[i], ynp[i], ynq[i]);
-                if (i == N - 1 && q >= y0 && q < y1) write_dual<TGV, S>(P, xs, q, ynp[i], ynq[i]);
+                    dual_at<TGV>(p_in, q_in, t_q, flag(i), ub, vb, ub_r, vb_r, xbu[i][o], xbv[i][o], a0, a1,
+                                 a.sigma_n[i], sqn[i], pn, qn);
+                if (i == N - 1 && q >= y0 && q < y1) write_dual<TGV, S>(P, xs, q, pn, qn);
             }
-        }
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            xu[i] = xnu[i];
-            xv[i] = xnv[i];
-            xbu[i] = xbnu[i];
-            xbv[i] = xbnv[i];
-            yp[i] = ynp[i];
-            yq[i] = ynq[i];
+            yp[i][s] = pn;
+            yq[i][s] = qn;
         }
         c = nx;
+    };
+    for (int r = r_hi; r >= r_lo; r -= 2) {
+        step(r, Par<0>());
+        __builtin_amdgcn_sched_barrier(0);
+        if (r - 1 >= r_lo) step(r - 1, Par<1>());
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -1143,10 +1157,17 @@ __global__ __launch_bounds__(kLanes * kWaves, (N == 4 || S != ST_F32) ? 4 : 1) v
     const int y0 = tk.y0;
     if (y0 >= P.H) return;
     const int y1 = min(y0 + by, P.H);
+    // the four-iteration kernels' LDS ring of row constants (RowConsts): 2N
+    // slots per wavefront, of which an upward march uses N
+    using TRaw = typename TensorRaw<S>::type;
+    constexpr int RW = N >= 4 ? kWaves : 1, RD = N >= 4 ? 2 * N : 1;
+    __shared__ TRaw ringT[RW][RD][kLanes];
+    __shared__ float ringR[RW][RD][kLanes];
+    const int wv = N >= 4 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes) : 0;
     if ((y0 / by) & 1)
-        march_up<TGV, S, N>(a, P, x, owner, y0, y1);
+        march_up<TGV, S, N>(a, P, x, owner, y0, y1, ringT[wv], ringR[wv]);
     else
-        march_down<TGV, S, N>(a, P, x, owner, y0, y1);
+        march_down<TGV, S, N>(a, P, x, owner, y0, y1, ringT[wv], ringR[wv]);
 }
 
 // Wavefronts of a kernel that the current device holds at once (its
