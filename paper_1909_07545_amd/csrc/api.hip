@@ -256,13 +256,12 @@ vfs_status check_params(const vfs_params* p)
 
 // Iterations per pass of the dominant primal-dual launches for pairs whose
 // level 0 is g's, in a storage mode, unless `requested` (2, 3 or 4) fixes it.
-// Measured on MI355X (8 pairs of 2048x2048, whole solve): where the passes
-// are bandwidth-bound (2048x2048 pairs), four iterations per pass in FP32
-// (138.3 Gpix-iter/s against 131.0 with three; the four-iteration kernel
-// keeps its row constants in LDS and runs four wavefronts per SIMD) and
-// three with 16-bit storage (162.4 against 146.0 with four: that kernel is
-// bound by vector issue, and a fourth iteration adds halo work); two where
-// the launches are latency-bound (pairs up to 1280x1024, alone or in serving
+// Measured on MI355X (8 pairs of 2048x2048, whole solve): on these pairs
+// four iterations per pass in FP32 (157.5 Gpix-iter/s against 133.2 with
+// three; an earlier build 138.3 against 131.0) and three with 16-bit storage
+// (171.6 against 156.5 with four: the 16-bit kernels spend more of their
+// vector issue per iteration, and a fourth iteration adds halo work); two
+// where the launches are latency-bound (pairs up to 1280x1024, alone or in serving
 // buckets).  The choice depends on the pair's size and the storage only, not
 // on how many pairs share a launch, so that a pair's result does not depend
 // on its batch (16-bit storage rounds the duals at pass boundaries; in FP32

@@ -68,26 +68,29 @@ constexpr int kBY = 16;
 // (measured on 8 pairs of 2048x2048: 552 us per launch at 16 rows, 517 at
 // 28, 520 at 36; FP32 is slower beyond 16: 677, 685 at 22, 693 at 28).
 constexpr int kBY16 = 28;
-// The FP32 four-iteration kernel is issue-bound too: its marches aim at 32
-// rows (measured on 8 pairs of 2048x2048: 817 us per launch at a 16-row
-// target, 779 at 24, 770 at 32 -- 30-row marches in five rounds; a target
-// that leaves fewer than kRoundsForShort rounds falls back to one round of
-// long marches, 801 us).
-constexpr int kBY4 = 32;
+// The FP32 four-iteration kernel is issue-bound too: its marches aim at 40
+// rows (measured on 8 pairs of 2048x2048 with carried step-size bases, three
+// wavefronts per SIMD: 735 us per launch at a 24-row target, 726 at 32, 719
+// at 40 -- 41-row marches in five rounds; without carried bases, four
+// wavefronts per SIMD: 817 us at 16, 779 at 24, 770 at 32).  A target that
+// leaves fewer than kRoundsForShort rounds falls back to one round of long
+// marches.
+constexpr int kBY4 = 40;
 constexpr int kBYs = 4;
 constexpr long long kRoundsForShort = 4;
 constexpr int kXcds = 8;
 
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // whole-wavefront shifts by one lane (DPP wave_shr:1 / wave_shl:1); the lane
-// without a source receives 0 -- always a halo lane whose result is unused
+// without a source receives 0 (bound_ctrl: no old value to set up) -- always
+// a halo lane whose result is unused
 __device__ inline float from_left(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, true));
 }
 __device__ inline float from_right(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, true));
 }
 
 struct Row {
@@ -758,16 +761,16 @@ template <> struct TensorRaw<ST_F32> {
 };
 
 // The row constants (tensor pack as stored, rho_c) of the last D rows of a
-// downward march: a register delay line shifted at every step, or a ring in
-// LDS, one per wavefront, where the row entering at a step takes slot h, row
-// r - d sits at slot (h + d) mod D and h steps back by one per step.  The
-// ring holds the four-iteration kernels' eight rows out of the registers:
-// 122 VGPRs instead of 140 in FP32 (four wavefronts per SIMD instead of
-// three, with 40 KB of LDS per workgroup), and 2048x2048 pairs then run four
-// iterations per pass faster than three (measured; see pd_pass_iters).  The
-// three-iteration kernels keep their six rows in registers: the ring saves
-// them no wavefront and its index arithmetic costs as much as the moves it
-// saves (measured: equal times).
+// march: a register delay line shifted at every step, or a ring in LDS, one
+// per wavefront, where the row entering at a step takes slot h, the row that
+// entered d steps earlier sits at slot (h + d) mod D and h steps back by one
+// per step.  The ring holds the four-iteration kernels' rows out of the
+// registers (40 KB of LDS per workgroup): with it and the carried step-size
+// bases they take 150 VGPRs in FP32, three wavefronts per SIMD; with the rows
+// in registers as well they would drop to two.  The three-iteration kernels
+// keep their six rows in registers: the ring saves them no wavefront and its
+// index arithmetic costs as much as the moves it saves (measured: equal
+// times).
 template <typename TRaw, int D, bool RING> struct RowConsts {
     TRaw t[D];
     float rho[D];
@@ -825,10 +828,13 @@ template <typename TRaw, int D> struct RowConsts<TRaw, D, true> {
 
 // Whether a march computes each row's step-size bases once, when the row
 // enters, and carries them in a delay line beside the tensor, or at every use.
-// Both give the same values.  Carried where the registers fit without losing
-// a wavefront per SIMD: the TGV kernels of three iterations (FP32 125 VGPRs,
-// 16-bit 118); the four-iteration kernels would drop one.
-template <bool TGV, int S, int N> constexpr bool kCarryBases = TGV && N == 3;
+// Both give the same values.  Carried in the TGV kernels of three and four
+// iterations: the three-iteration kernels keep four wavefronts per SIMD with
+// them (FP32 133 VGPRs is the exception, three), the four-iteration ones drop
+// to three (150 VGPRs in FP32) and are still faster: their marches issue 12 to
+// 15 % fewer vector instructions (measured on 8 pairs of 2048x2048: 738 ->
+// 726 us per launch at the same march height).
+template <bool TGV, int S, int N> constexpr bool kCarryBases = TGV && N >= 3;
 
 // A step's parity as a type: the marches run two steps per loop trip, so
 // that the slot of a two-step window that a step reads or writes is a
@@ -991,11 +997,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
     };
     for (int r = r_lo; r <= r_hi; r += 2) {
         step(r, Par<0>());
-        // keep the two steps apart: interleaved, they would need more
-        // registers than four wavefronts per SIMD leave
-        __builtin_amdgcn_sched_barrier(0);
         if (r + 1 <= r_hi) step(r + 1, Par<1>());
-        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -1050,13 +1052,17 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
     }
     const int r_hi = y1 + N - 1, r_lo = y0 - (N - 1);
     const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
-    // the current row (rows in two slots instead, the registers exceed what
-    // four wavefronts per SIMD leave)
-    Row c = read_row<TGV, true, S>(P, x, r_hi);
+    // the current row and the row above it, in slots as above: the row above
+    // of one step is the current row of the next
+    Row rw[2];
+    rw[0] = zero_row();
+    rw[1] = read_row<TGV, true, S>(P, x, r_hi);
     auto step = [&](const int r, auto par) {
         constexpr int s = decltype(par)::v, o = s ^ 1;
         // the row above: iteration 0's y^k there, and the next step's row
-        const Row nx = read_row<TGV, true, S>(P, x, r - 1);
+        rw[s] = read_row<TGV, true, S>(P, x, r - 1);
+        const Row& c = rw[o];
+        const Row& nx = rw[s];
         K.push(TensorRaw<S>::pack(c.t), c.rho);
         fD = (fD << 8) | c.f;
         if constexpr (CB) {
@@ -1123,13 +1129,10 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
             yp[i][s] = pn;
             yq[i][s] = qn;
         }
-        c = nx;
     };
     for (int r = r_hi; r >= r_lo; r -= 2) {
         step(r, Par<0>());
-        __builtin_amdgcn_sched_barrier(0);
         if (r - 1 >= r_lo) step(r - 1, Par<1>());
-        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -1140,7 +1143,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
 // on the same inputs, so each pixel's result does not depend on the
 // direction (this file contracts multiply-adds only within one expression).
 template <bool TGV, int S, int N>
-__global__ __launch_bounds__(kLanes * kWaves, (N == 4 || S != ST_F32) ? 4 : 1) void pdn_kernel(PdArgs a, int by,
+__global__ __launch_bounds__(kLanes * kWaves, N == 4 ? 3 : (S != ST_F32 ? 4 : 1)) void pdn_kernel(PdArgs a, int by,
                                                                                                int segs)
 {
     constexpr int kColsN = kLanes - 2 * N;
