@@ -273,14 +273,21 @@ int pd_pass_iters(const Geometry& g, int requested, int storage)
     return storage == VFS_F32 ? 4 : 3;
 }
 
+// Whether the K iterations of a warp start with a multi-iteration pass whose
+// first iteration is the dual half alone (PD_FIRST3 / 4) rather than with a
+// PD_DUAL_FIRST launch: with passes of three or four iterations, K >= NP.
+static bool first_pass(int K, int NP) { return NP >= 3 && K >= NP; }
+
 void pd_parity(int K, int NP, int& pu, int& pp)
 {
     pu = pp = 0;
     if (K <= 0) return;
-    const int rem = (K - 1) % NP, passes = (K - 1) / NP;
-    const int both = rem % 2 + rem / 2 + passes;  // launches that flip both copies
-    pp = (1 + both) & 1;                           // plus the first (dual only)
-    pu = (both + 1) & 1;                           // plus the last (primal only)
+    const bool fp = first_pass(K, NP);
+    const int k0 = fp ? NP : 1;                      // the first iteration left after the start
+    const int rem = (K - k0) % NP, passes = (K - k0) / NP;
+    const int both = rem % 2 + rem / 2 + passes + (fp ? 1 : 0);  // launches that flip both copies
+    pp = (both + (fp ? 0 : 1)) & 1;                  // plus PD_DUAL_FIRST (dual only)
+    pu = (both + 1) & 1;                             // plus the last (primal only)
 }
 
 int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
@@ -294,17 +301,34 @@ int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s,
         a.lc.ip = ip;
         launch_pd(a, s);
     };
-    a.mode = PD_DUAL_FIRST;
-    a.tau_scale = 1.f;
-    a.sigma_scale = 1.f / sc.s[0];
-    a.theta = 1.f;
-    go();
-    ip ^= 1;
-    // iterations 1 .. K-1: the remainder first (one alone, then a pair),
-    // then passes of NP iterations each
     const int NP = base.pass;
     int k = 1;
-    int rem = (K - 1) % NP;
+    if (first_pass(K, NP)) {
+        // y^1 and iterations 1 .. NP-1 in one pass
+        a.mode = NP == 3 ? PD_FIRST3 : PD_FIRST4;
+        a.tau_n[0] = 1.f;
+        a.theta_n[0] = 1.f;
+        a.sigma_n[0] = 1.f / sc.s[0];
+        for (int i = 1; i < NP; ++i) {
+            a.tau_n[i] = sc.s[i - 1];
+            a.theta_n[i] = sc.theta[i - 1];
+            a.sigma_n[i] = 1.f / sc.s[i];
+        }
+        go();
+        iu ^= 1;
+        ip ^= 1;
+        k = NP;
+    } else {
+        a.mode = PD_DUAL_FIRST;
+        a.tau_scale = 1.f;
+        a.sigma_scale = 1.f / sc.s[0];
+        a.theta = 1.f;
+        go();
+        ip ^= 1;
+    }
+    // iterations k .. K-1: the remainder first (one alone, then a pair),
+    // then passes of NP iterations each
+    int rem = (K - k) % NP;
     if (rem % 2) {
         a.mode = PD_FUSED;
         a.tau_scale = sc.s[k - 1];

@@ -13,8 +13,11 @@
 // march, reading the first one's results from registers, so the state is read
 // and written once per two iterations.  A warp's K iterations are one
 // PD_DUAL_FIRST launch (y^1 from x^0 = xbar^0), (K-1) iterations of
-// PD_FUSED2 / PD_FUSED launches and one PD_PRIMAL_LAST launch (x^K).  Every
-// launch reads one copy of the state and writes the other.
+// PD_FUSED2 / PD_FUSED launches and one PD_PRIMAL_LAST launch (x^K); with
+// passes of N = 3 or 4 iterations (pdn_kernel) the first launch is a pass
+// whose first iteration is the dual half alone (PD_FIRST3 / 4), and N - 1
+// fewer iterations follow.  Every launch reads one copy of the state and
+// writes the other.
 //
 // Storage: p, q and the tensor pack are read and written as FP32, FP16 or
 // BF16 (template S); u, v, rho_c and all arithmetic are FP32.
@@ -845,7 +848,7 @@ template <int V> struct Par {
 
 // Downward march: at step r, iteration i takes its primal step at row r - 2i
 // and its dual step at row r - 2i - 1 (the dual needs xbar of the row below).
-template <bool TGV, int S, int N>
+template <bool TGV, int S, int N, bool FIRST>
 __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int x, bool owner, int y0, int y1,
                                            typename TensorRaw<S>::type (*ringT)[kLanes], float (*ringR)[kLanes])
 {
@@ -964,16 +967,19 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             const float4 t_ab = TensorRaw<S>::unpack(K.tens(2 * i + 1));
             const Above ab = i == 0 ? above_of(pm[o], qm[o], t_ab, flag(1))
                                     : above_of(yp[i - 1][s], yq[i - 1][s], t_ab, flag(2 * i + 1));
-            float un;
-            float2 vn;
+            float un = u_in;
+            float2 vn = v_in;
             const float4 t_q = i == 0 ? c.t : TensorRaw<S>::unpack(K.tens(2 * i));
             const float rho_q = i == 0 ? c.rho : K.rh(2 * i);
-            if constexpr (CB)
+            if (FIRST && i == 0) {
+                // the first half iteration: no primal step (xbar^0 = x^0)
+            } else if constexpr (CB) {
                 primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rho_q, flag(2 * i), ab, a0, a1, lam,
                                  tuD[2 * i] * a.tau_n[i], tvD[2 * i] * a.tau_n[i], un, vn);
-            else
+            } else {
                 primal_at<TGV>(u_in, v_in, p_in, q_in, t_q, rho_q, flag(2 * i), ab, a0, a1, lam, a.tau_n[i],
                                un, vn);
+            }
             const float th = a.theta_n[i];
             const float ubn = un + th * (un - u_in);
             const float2 vbn = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
@@ -1018,7 +1024,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
 // dual step needs xbar of the row below, from iteration i's previous step.
 // Iteration i covers the same rows as in the downward march, so every value
 // is computed from the same inputs.
-template <bool TGV, int S, int N>
+template <bool TGV, int S, int N, bool FIRST>
 __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x, bool owner, int y0, int y1,
                                          typename TensorRaw<S>::type (*ringT)[kLanes], float (*ringR)[kLanes])
 {
@@ -1120,11 +1126,16 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
                 const Above ab = i == 0 ? above_of(nx.p, nx.q, nx.t, nx.f)
                                         : above_of(yp[i - 1][s], yq[i - 1][s],
                                                    i == 1 ? c.t : TensorRaw<S>::unpack(K.tens(i - 1)), flag(i - 1));
-                if constexpr (CB)
+                if (FIRST && i == 0) {
+                    // the first half iteration: no primal step (xbar^0 = x^0)
+                    un = u_in;
+                    vn = v_in;
+                } else if constexpr (CB) {
                     primal_step<TGV>(u_in, v_in, p_in, q_in, t_q, rho_q, flag(i), ab, a0, a1, lam, tuD[i] * a.tau_n[i],
                                      tvD[i] * a.tau_n[i], un, vn);
-                else
+                } else {
                     primal_at<TGV>(u_in, v_in, p_in, q_in, t_q, rho_q, flag(i), ab, a0, a1, lam, a.tau_n[i], un, vn);
+                }
                 const float th = a.theta_n[i];
                 ub = un + th * (un - u_in);
                 vb = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
@@ -1163,7 +1174,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
 // and the second read hits in L2.  Both marches call the same step functions
 // on the same inputs, so each pixel's result does not depend on the
 // direction (this file contracts multiply-adds only within one expression).
-template <bool TGV, int S, int N>
+template <bool TGV, int S, int N, bool FIRST>
 __global__ __launch_bounds__(kLanes * kWaves, N == 4 ? 3 : (S != ST_F32 ? 4 : 1)) void pdn_kernel(PdArgs a, int by,
                                                                                                int segs)
 {
@@ -1189,9 +1200,9 @@ __global__ __launch_bounds__(kLanes * kWaves, N == 4 ? 3 : (S != ST_F32 ? 4 : 1)
     __shared__ float ringR[RW][RD][kLanes];
     const int wv = N >= 4 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes) : 0;
     if ((y0 / by) & 1)
-        march_up<TGV, S, N>(a, P, x, owner, y0, y1, ringT[wv], ringR[wv]);
+        march_up<TGV, S, N, FIRST>(a, P, x, owner, y0, y1, ringT[wv], ringR[wv]);
     else
-        march_down<TGV, S, N>(a, P, x, owner, y0, y1, ringT[wv], ringR[wv]);
+        march_down<TGV, S, N, FIRST>(a, P, x, owner, y0, y1, ringT[wv], ringR[wv]);
 }
 
 // Wavefronts of a kernel that the current device holds at once (its
@@ -1299,13 +1310,13 @@ void launch_fused2(const PdArgs& a, hipStream_t s)
         hipLaunchKernelGGL((pd2_kernel<TGV, S>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
 
-template <bool TGV, int S, int N>
+template <bool TGV, int S, int N, bool FIRST>
 void launch_fusedn(const PdArgs& a, hipStream_t s)
 {
-    const March m = march_shape(a, kLanes - 2 * N, pdn_kernel<TGV, S, N>, short_march_floor(a, kLanes - 2 * N),
+    const March m = march_shape(a, kLanes - 2 * N, pdn_kernel<TGV, S, N, FIRST>, short_march_floor(a, kLanes - 2 * N),
                                 S == ST_F32 ? (N == 4 ? kBY4 : kBY) : kBY16);
     if (m.blocks)
-        hipLaunchKernelGGL((pdn_kernel<TGV, S, N>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
+        hipLaunchKernelGGL((pdn_kernel<TGV, S, N, FIRST>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
 
 template <bool TGV, int S>
@@ -1314,8 +1325,10 @@ void launch_typed(const PdArgs& a, hipStream_t s)
     if (a.mode == PD_DUAL_FIRST) launch_mode<PD_DUAL_FIRST, TGV, S>(a, s);
     else if (a.mode == PD_FUSED) launch_mode<PD_FUSED, TGV, S>(a, s);
     else if (a.mode == PD_FUSED2) launch_fused2<TGV, S>(a, s);
-    else if (a.mode == PD_FUSED3) launch_fusedn<TGV, S, 3>(a, s);
-    else if (a.mode == PD_FUSED4) launch_fusedn<TGV, S, 4>(a, s);
+    else if (a.mode == PD_FUSED3) launch_fusedn<TGV, S, 3, false>(a, s);
+    else if (a.mode == PD_FUSED4) launch_fusedn<TGV, S, 4, false>(a, s);
+    else if (a.mode == PD_FIRST3) launch_fusedn<TGV, S, 3, true>(a, s);
+    else if (a.mode == PD_FIRST4) launch_fusedn<TGV, S, 4, true>(a, s);
     else launch_mode<PD_PRIMAL_LAST, TGV, S>(a, s);
 }
 
@@ -1326,8 +1339,10 @@ void prepare_typed()
     (void)resident_waves(pd_kernel<PD_FUSED, TGV, S>);
     (void)resident_waves(pd_kernel<PD_PRIMAL_LAST, TGV, S>);
     (void)resident_waves(pd2_kernel<TGV, S>);
-    (void)resident_waves(pdn_kernel<TGV, S, 3>);
-    (void)resident_waves(pdn_kernel<TGV, S, 4>);
+    (void)resident_waves(pdn_kernel<TGV, S, 3, false>);
+    (void)resident_waves(pdn_kernel<TGV, S, 4, false>);
+    (void)resident_waves(pdn_kernel<TGV, S, 3, true>);
+    (void)resident_waves(pdn_kernel<TGV, S, 4, true>);
 }
 
 }  // namespace
