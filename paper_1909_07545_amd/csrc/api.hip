@@ -274,9 +274,9 @@ int pd_pass_iters(const Geometry& g, int requested, int storage)
 }
 
 // Whether the K iterations of a warp start with a multi-iteration pass whose
-// first iteration is the dual half alone (PD_FIRST3 / 4) rather than with a
-// PD_DUAL_FIRST launch: with passes of three or four iterations, K >= NP.
-static bool first_pass(int K, int NP) { return NP >= 3 && K >= NP; }
+// first iteration is the dual half alone (PD_FIRST2 / 3 / 4) rather than with
+// a PD_DUAL_FIRST launch: whenever K >= NP.
+static bool first_pass(int K, int NP) { return NP >= 2 && K >= NP; }
 
 void pd_parity(int K, int NP, int& pu, int& pp)
 {
@@ -305,7 +305,7 @@ int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s,
     int k = 1;
     if (first_pass(K, NP)) {
         // y^1 and iterations 1 .. NP-1 in one pass
-        a.mode = NP == 3 ? PD_FIRST3 : PD_FIRST4;
+        a.mode = NP == 2 ? PD_FIRST2 : NP == 3 ? PD_FIRST3 : PD_FIRST4;
         a.tau_n[0] = 1.f;
         a.theta_n[0] = 1.f;
         a.sigma_n[0] = 1.f / sc.s[0];
@@ -342,12 +342,11 @@ int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s,
     }
     for (; rem >= 2; rem -= 2, k += 2) {
         a.mode = PD_FUSED2;
-        a.tau_scale = sc.s[k - 1];
-        a.theta = sc.theta[k - 1];
-        a.sigma_scale = 1.f / sc.s[k];
-        a.tau_scale2 = sc.s[k];
-        a.theta2 = sc.theta[k];
-        a.sigma_scale2 = 1.f / sc.s[k + 1];
+        for (int i = 0; i < 2; ++i) {
+            a.tau_n[i] = sc.s[k + i - 1];
+            a.theta_n[i] = sc.theta[k + i - 1];
+            a.sigma_n[i] = 1.f / sc.s[k + i];
+        }
         go();
         iu ^= 1;
         ip ^= 1;
@@ -355,21 +354,11 @@ int run_pd(PdArgs base, const Sched& sc, int K, int& iu, int& ip, hipStream_t s,
     if (ev0) (void)hipEventRecord(ev0, s);
     int passes = 0;
     for (; k + NP - 1 <= K - 1; k += NP, ++passes) {
-        if (NP == 2) {
-            a.mode = PD_FUSED2;
-            a.tau_scale = sc.s[k - 1];
-            a.theta = sc.theta[k - 1];
-            a.sigma_scale = 1.f / sc.s[k];
-            a.tau_scale2 = sc.s[k];
-            a.theta2 = sc.theta[k];
-            a.sigma_scale2 = 1.f / sc.s[k + 1];
-        } else {
-            a.mode = NP == 3 ? PD_FUSED3 : PD_FUSED4;
-            for (int i = 0; i < NP; ++i) {
-                a.tau_n[i] = sc.s[k + i - 1];
-                a.theta_n[i] = sc.theta[k + i - 1];
-                a.sigma_n[i] = 1.f / sc.s[k + i];
-            }
+        a.mode = NP == 2 ? PD_FUSED2 : NP == 3 ? PD_FUSED3 : PD_FUSED4;
+        for (int i = 0; i < NP; ++i) {
+            a.tau_n[i] = sc.s[k + i - 1];
+            a.theta_n[i] = sc.theta[k + i - 1];
+            a.sigma_n[i] = 1.f / sc.s[k + i];
         }
         go();
         iu ^= 1;

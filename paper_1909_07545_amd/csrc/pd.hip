@@ -8,16 +8,15 @@
 // with x = (u, v), y = (p, q), but the state in memory is stored one half
 // step apart, (x^{k-1}, y^k).  A PD_FUSED launch computes x^k on the tile plus
 // a one-pixel halo, forms xbar^k in registers and finishes with y^{k+1}; xbar
-// never touches memory.  A PD_FUSED2 launch does two such iterations in one
-// pass over memory: the second trails the first by two rows in the same
-// march, reading the first one's results from registers, so the state is read
-// and written once per two iterations.  A warp's K iterations are one
-// PD_DUAL_FIRST launch (y^1 from x^0 = xbar^0), (K-1) iterations of
-// PD_FUSED2 / PD_FUSED launches and one PD_PRIMAL_LAST launch (x^K); with
-// passes of N = 3 or 4 iterations (pdn_kernel) the first launch is a pass
-// whose first iteration is the dual half alone (PD_FIRST3 / 4), and N - 1
-// fewer iterations follow.  Every launch reads one copy of the state and
-// writes the other.
+// never touches memory.  A PD_FUSED2 / 3 / 4 launch (pdn_kernel) does N = 2,
+// 3 or 4 such iterations in one pass over memory: each trails the one before
+// by two rows in the same march, reading its results from registers, so the
+// state is read and written once per N iterations.  A warp's K iterations
+// (K >= N) are one PD_FIRST2 / 3 / 4 pass (the same pass whose first
+// iteration is the dual half alone, y^1 from x^0 = xbar^0), the remaining
+// K - N iterations in PD_FUSED / PD_FUSED2 launches and passes of N, and one
+// PD_PRIMAL_LAST launch (x^K); with K < N a PD_DUAL_FIRST launch starts it.
+// Every launch reads one copy of the state and writes the other.
 //
 // Storage: p, q and the tensor pack are read and written as FP32, FP16 or
 // BF16 (template S); u, v, rho_c and all arithmetic are FP32.
@@ -27,8 +26,8 @@
 // the largest, workgroups beyond a pair's level exit at once).
 //
 // Work decomposition: one 64-lane wavefront owns a strip of columns (62 for
-// the one-iteration modes: lanes 1..62, lanes 0 and 63 are the x-halo; 60 for
-// PD_FUSED2: lanes 2..61; 64 - 2N for N iterations) and marches down a
+// the one-iteration modes: lanes 1..62, lanes 0 and 63 are the x-halo;
+// 64 - 2N for N iterations) and marches down a
 // segment of rows plus a halo above and below, keeping the rows it still
 // needs in registers and exchanging x-neighbours by lane shifts.  The four
 // wavefronts of a workgroup take four neighbouring strips of the same
@@ -56,7 +55,6 @@ namespace {
 constexpr int kLanes = 64;
 constexpr int kWaves = 4;            // wavefronts per workgroup
 constexpr int kCols = kLanes - 2;    // owned columns per wavefront, one-iteration modes
-constexpr int kCols2 = kLanes - 4;   // owned columns per wavefront, PD_FUSED2
 // Segment heights (rows per wavefront march).  With enough work for several
 // rounds of resident wavefronts: marches of about kBY rows, their count
 // rounded to whole rounds (short marches keep the rows in flight at any
@@ -564,172 +562,8 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd_kernel(PdArgs a, int by, i
     }
 }
 
-// Two iterations per pass (PD_FUSED2): (x^{k-1}, y^k) -> (x^{k+1}, y^{k+2}).
-// At step r of the march: A = primal of iteration 1 at row r, B = dual of
-// iteration 1 at row r-1, C = primal of iteration 2 at row r-2 (reads A's
-// x^k and B's y^{k+1} from registers), D = dual of iteration 2 at row r-3.
-// The wavefront owns rows [y0, y1) and marches r = y0-1 .. y1+2 (row y0-2 is
-// read for A's first "above").  Column validity shrinks by one lane per
-// stage away from the wavefront's edges: A is exact on lanes 1..63, B on
-// 1..62, C on 2..62, D on 2..61 -- the owned lanes.
-template <bool TGV, int S>
-__global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, int segs)
-{
-    Task tk;
-    if (!task_of(a, kCols2, by, segs, tk)) return;
-    Planes P;
-    if (!planes_of<S>(a, tk.pair, P)) return;
-    const int tx = tk.tx;
-    if (tx * kCols2 >= P.W) return;
-
-    const int lane = threadIdx.x & (kLanes - 1);
-    const int x = tx * kCols2 - 2 + lane;
-    const bool owner = lane >= 2 && lane <= kCols2 + 1 && x < P.W;
-    const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
-    const int y0 = tk.y0;
-    if (y0 >= P.H) return;
-    const int y1 = min(y0 + by, P.H);
-    const float a0 = a.alpha0, a1 = a.alpha1, lam = a.lambda;
-    const float sq1 = a.sigma_scale / (2.f * a0), sq2 = a.sigma_scale2 / (2.f * a0);
-
-    // iteration 1: "above" of row r-1, and row r-1 as B needs it
-    Above ab1;
-    {
-        const Row w = read_row<TGV, false, S>(P, x, y0 - 2);
-        ab1 = above_of(w.p, w.q, w.t, w.f);
-    }
-    float2 p_m1 = make_float2(0.f, 0.f);
-    float4 q_m1 = make_float4(0.f, 0.f, 0.f, 0.f), t_m1 = make_float4(1.f, 0.f, 1.f, 0.f);
-    unsigned f_m1 = 0u;
-    float rho_m1 = 0.f, ub1_m1 = 0.f;
-    float2 vb1_m1 = make_float2(0.f, 0.f);
-    // x^k of rows r-1, r-2 (A's results), constants of rows r-2, r-3
-    float un1_m1 = 0.f, un1_m2 = 0.f;
-    float2 vn1_m1 = make_float2(0.f, 0.f), vn1_m2 = make_float2(0.f, 0.f);
-    float4 t_m2 = make_float4(1.f, 0.f, 1.f, 0.f), t_m3 = make_float4(1.f, 0.f, 1.f, 0.f);
-    float rho_m2 = 0.f;
-    unsigned f_m2 = 0u, f_m3 = 0u;
-    // y^{k+1} of rows r-2, r-3 (B's results); "above" of iteration 2; xbar^{k+1} of row r-3
-    float2 p1_m2 = make_float2(0.f, 0.f), p1_m3 = make_float2(0.f, 0.f);
-    float4 q1_m2 = make_float4(0.f, 0.f, 0.f, 0.f), q1_m3 = make_float4(0.f, 0.f, 0.f, 0.f);
-    Above ab2 = {0.f, 0.f, 0.f, 0.f, 0.f};
-    float ub2_m3 = 0.f;
-    float2 vb2_m3 = make_float2(0.f, 0.f);
-    // TGV: each row's step-size bases, computed once when A reaches the row
-    // and carried to C (primal, two steps later) and to B and D (dual, one
-    // and three steps later); the row above contributes its tensor and mask
-    // bits only, which A and C see alike
-    float tu_m1 = 0.f, tu_m2 = 0.f, tv_m1 = 0.f, tv_m2 = 0.f, sg_m1 = 0.f, sg_m2 = 0.f, sg_m3 = 0.f;
-
-    // rows are loaded one step ahead of their use (see pd_kernel)
-    constexpr bool PF = true;
-    Row nxt = zero_row();
-    if constexpr (PF) nxt = read_row<TGV, true, S>(P, x, y0 - 1);
-    for (int r = y0 - 1; r <= y1 + 2; ++r) {
-        // A: iteration-1 primal at row r
-        Row c = zero_row();
-        float un1 = 0.f, ub1 = 0.f, tu0 = 0.f, tv0 = 0.f, sg0 = 0.f;
-        float2 vn1 = make_float2(0.f, 0.f), vb1 = make_float2(0.f, 0.f);
-        if (r <= y1 + 1) {
-            if constexpr (PF) {
-                c = nxt;
-                if (r + 1 <= y1 + 1) nxt = read_row<TGV, true, S>(P, x, r + 1);
-            } else {
-                c = read_row<TGV, true, S>(P, x, r);
-            }
-            if constexpr (TGV) {
-                const PrimalBases b = primal_bases<TGV>(c.t, c.f, ab1.cy, ab1.my, a0, a1);
-                tu0 = b.tu;
-                tv0 = b.tv;
-                sg0 = dual_base<TGV>(c.t, c.f, a1);
-                primal_step<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, tu0 * a.tau_scale,
-                                 tv0 * a.tau_scale, un1, vn1);
-            } else {
-                primal_at<TGV>(c.u, c.v, c.p, c.q, c.t, c.rho, c.f, ab1, a0, a1, lam, a.tau_scale, un1, vn1);
-            }
-            ub1 = un1 + a.theta * (un1 - c.u);
-            vb1 = make_float2(vn1.x + a.theta * (vn1.x - c.v.x), vn1.y + a.theta * (vn1.y - c.v.y));
-        }
-        // B: iteration-1 dual at row r-1 -> y^{k+1}(r-1)
-        float2 p1 = make_float2(0.f, 0.f);
-        float4 q1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r >= y0 && r <= y1 + 1) {
-            const float ub_r = from_right(ub1_m1);
-            const float2 vb_r = make_float2(from_right(vb1_m1.x), from_right(vb1_m1.y));
-            if constexpr (TGV)
-                dual_step<TGV>(p_m1, q_m1, t_m1, f_m1, ub1_m1, vb1_m1, ub_r, vb_r, ub1, vb1, a0, a1,
-                               sg_m1 * a.sigma_scale, sq1, p1, q1);
-            else
-                dual_at<TGV>(p_m1, q_m1, t_m1, f_m1, ub1_m1, vb1_m1, ub_r, vb_r, ub1, vb1, a0, a1, a.sigma_scale,
-                             sq1, p1, q1);
-        }
-        // C: iteration-2 primal at row r-2 -> x^{k+1}(r-2)
-        float ub2 = 0.f;
-        float2 vb2 = make_float2(0.f, 0.f);
-        if (r >= y0 + 2) {
-            float un2;
-            float2 vn2;
-            if constexpr (TGV)
-                primal_step<TGV>(un1_m2, vn1_m2, p1_m2, q1_m2, t_m2, rho_m2, f_m2, ab2, a0, a1, lam,
-                                 tu_m2 * a.tau_scale2, tv_m2 * a.tau_scale2, un2, vn2);
-            else
-                primal_at<TGV>(un1_m2, vn1_m2, p1_m2, q1_m2, t_m2, rho_m2, f_m2, ab2, a0, a1, lam, a.tau_scale2,
-                               un2, vn2);
-            ub2 = un2 + a.theta2 * (un2 - un1_m2);
-            vb2 = make_float2(vn2.x + a.theta2 * (vn2.x - vn1_m2.x), vn2.y + a.theta2 * (vn2.y - vn1_m2.y));
-            if (r - 2 < y1) write_primal<TGV>(P, xs, r - 2, un2, vn2);
-        }
-        // D: iteration-2 dual at row r-3 -> y^{k+2}(r-3)
-        if (r >= y0 + 3) {
-            const float ub_r = from_right(ub2_m3);
-            const float2 vb_r = make_float2(from_right(vb2_m3.x), from_right(vb2_m3.y));
-            float2 pn;
-            float4 qn;
-            if constexpr (TGV)
-                dual_step<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1,
-                               sg_m3 * a.sigma_scale2, sq2, pn, qn);
-            else
-                dual_at<TGV>(p1_m3, q1_m3, t_m3, f_m3, ub2_m3, vb2_m3, ub_r, vb_r, ub2, vb2, a0, a1,
-                             a.sigma_scale2, sq2, pn, qn);
-            write_dual<TGV, S>(P, xs, r - 3, pn, qn);
-        }
-        // slide the windows (deepest first)
-        tu_m2 = tu_m1;
-        tu_m1 = tu0;
-        tv_m2 = tv_m1;
-        tv_m1 = tv0;
-        sg_m3 = sg_m2;
-        sg_m2 = sg_m1;
-        sg_m1 = sg0;
-        ab2 = above_of(p1_m2, q1_m2, t_m2, f_m2);      // row r-2, for C at row r-1
-        t_m3 = t_m2;
-        f_m3 = f_m2;
-        p1_m3 = p1_m2;
-        q1_m3 = q1_m2;
-        ub2_m3 = ub2;
-        vb2_m3 = vb2;
-        t_m2 = t_m1;
-        f_m2 = f_m1;
-        rho_m2 = rho_m1;
-        p1_m2 = p1;
-        q1_m2 = q1;
-        un1_m2 = un1_m1;
-        vn1_m2 = vn1_m1;
-        un1_m1 = un1;
-        vn1_m1 = vn1;
-        p_m1 = c.p;
-        q_m1 = c.q;
-        t_m1 = c.t;
-        f_m1 = c.f;
-        rho_m1 = c.rho;
-        ub1_m1 = ub1;
-        vb1_m1 = vb1;
-        ab1 = above_of(c.p, c.q, c.t, c.f);
-    }
-}
-
-// N iterations per pass (PD_FUSEDN): (x^{k-1}, y^k) -> (x^{k+N-1}, y^{k+N}),
-// the generalisation of pd2_kernel.  At march step r, iteration i (0-based)
+// N iterations per pass: (x^{k-1}, y^k) -> (x^{k+N-1}, y^{k+N}).  At march
+// step r, iteration i (0-based)
 // takes its primal step at row r - 2i and its dual step at row r - 2i - 1.
 // Iteration i's primal step reads x^{k+i-1} from iteration i-1's primal step
 // two steps earlier, y^{k+i} from iteration i-1's dual step one step earlier
@@ -739,7 +573,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void pd2_kernel(PdArgs a, int by, 
 // the last iteration produces exactly the owned rows [y0, y1).  Column
 // validity shrinks by one lane per iteration on each side: the wavefront
 // owns lanes N .. 63-N.  The row constants (tensor, rho_c, flags) of the
-// last 2N rows stay in registers.
+// last 2N rows stay in registers (or in LDS, RowConsts).
 // The tensor pack as kept in a register delay line: FP32 as is, the 16-bit
 // modes packed (as stored) and decoded at each use.
 template <int S> struct TensorRaw {
@@ -837,7 +671,7 @@ template <typename TRaw, int D> struct RowConsts<TRaw, D, true> {
 // to three (150 VGPRs in FP32) and are still faster: their marches issue 12 to
 // 15 % fewer vector instructions (measured on 8 pairs of 2048x2048: 738 ->
 // 726 us per launch at the same march height).
-template <bool TGV, int S, int N> constexpr bool kCarryBases = TGV && N >= 3;
+template <bool TGV, int S, int N> constexpr bool kCarryBases = TGV && N >= 2;
 
 // A step's parity as a type: the marches run two steps per loop trip, so
 // that the slot of a two-step window that a step reads or writes is a
@@ -1302,14 +1136,6 @@ void launch_mode(const PdArgs& a, hipStream_t s)
         hipLaunchKernelGGL((pd_kernel<MODE, TGV, S>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
 
-template <bool TGV, int S>
-void launch_fused2(const PdArgs& a, hipStream_t s)
-{
-    const March m = march_shape(a, kCols2, pd2_kernel<TGV, S>, short_march_floor(a, kCols2));
-    if (m.blocks)
-        hipLaunchKernelGGL((pd2_kernel<TGV, S>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
-}
-
 template <bool TGV, int S, int N, bool FIRST>
 void launch_fusedn(const PdArgs& a, hipStream_t s)
 {
@@ -1324,7 +1150,8 @@ void launch_typed(const PdArgs& a, hipStream_t s)
 {
     if (a.mode == PD_DUAL_FIRST) launch_mode<PD_DUAL_FIRST, TGV, S>(a, s);
     else if (a.mode == PD_FUSED) launch_mode<PD_FUSED, TGV, S>(a, s);
-    else if (a.mode == PD_FUSED2) launch_fused2<TGV, S>(a, s);
+    else if (a.mode == PD_FUSED2) launch_fusedn<TGV, S, 2, false>(a, s);
+    else if (a.mode == PD_FIRST2) launch_fusedn<TGV, S, 2, true>(a, s);
     else if (a.mode == PD_FUSED3) launch_fusedn<TGV, S, 3, false>(a, s);
     else if (a.mode == PD_FUSED4) launch_fusedn<TGV, S, 4, false>(a, s);
     else if (a.mode == PD_FIRST3) launch_fusedn<TGV, S, 3, true>(a, s);
@@ -1338,7 +1165,8 @@ void prepare_typed()
     (void)resident_waves(pd_kernel<PD_DUAL_FIRST, TGV, S>);
     (void)resident_waves(pd_kernel<PD_FUSED, TGV, S>);
     (void)resident_waves(pd_kernel<PD_PRIMAL_LAST, TGV, S>);
-    (void)resident_waves(pd2_kernel<TGV, S>);
+    (void)resident_waves(pdn_kernel<TGV, S, 2, false>);
+    (void)resident_waves(pdn_kernel<TGV, S, 2, true>);
     (void)resident_waves(pdn_kernel<TGV, S, 3, false>);
     (void)resident_waves(pdn_kernel<TGV, S, 4, false>);
     (void)resident_waves(pdn_kernel<TGV, S, 3, true>);

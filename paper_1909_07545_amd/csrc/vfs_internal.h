@@ -405,18 +405,17 @@ void launch_unrectify(const RectifyGeom& g, const float* field, const uint8_t* f
                       float* dst, size_t dst_pitch, uint8_t* valid, hipStream_t s);
 
 // Primal-dual iteration (Eq. (11)).
-// PD_FIRST3 / PD_FIRST4: a PD_FUSED3 / PD_FUSED4 pass whose first iteration is
+// PD_FIRST2 / 3 / 4: a pass of N = 2, 3, 4 iterations whose first iteration is
 // the dual half alone (PD_DUAL_FIRST followed by N - 1 iterations).
 enum PdMode {
     PD_DUAL_FIRST = 0, PD_FUSED = 1, PD_PRIMAL_LAST = 2, PD_FUSED2 = 3, PD_FUSED3 = 4, PD_FUSED4 = 5, PD_FIRST3 = 6,
-    PD_FIRST4 = 7
+    PD_FIRST4 = 7, PD_FIRST2 = 8
 };
 struct PdArgs {
     Launch lc;                  // parity (lc.iu, lc.ip): the state read; the other copy is written
     float alpha0, alpha1, lambda;
-    float tau_scale, sigma_scale, theta;     // iteration k (PD_FUSED2: the first of its two)
-    float tau_scale2, sigma_scale2, theta2;  // PD_FUSED2: iteration k + 1
-    float tau_n[4], sigma_n[4], theta_n[4];  // PD_FUSED3 / 4, PD_FIRST3 / 4: iterations k .. k + N - 1
+    float tau_scale, sigma_scale, theta;     // PD_DUAL_FIRST, PD_FUSED, PD_PRIMAL_LAST: iteration k
+    float tau_n[4], sigma_n[4], theta_n[4];  // PD_FUSED2 / 3 / 4, PD_FIRST2 / 3 / 4: iterations k .. k + N - 1
     int mode;                   // PdMode
     int tgv;                    // 1: TGV-L1 (Eq. (10)); 0: TV-L1 (v = 0, no q)
     int storage;                // Storage of p, q and the tensor pack
