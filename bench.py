@@ -124,11 +124,17 @@ def main():
     vfs.profile_enable(R, True)
     vfs.profile_read(R, reset=True)
     torch.cuda.synchronize()
+    # events between the steps on the stream the solves run on (no
+    # synchronisation inside the timed region): the spread of single steps
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
+    marks[0].record()
     for i in range(args.steps):
         outs = vfs.solve_batch(R, I0s, I1s, params, betas=betas, etas=etas, out=outs)
+        marks[i + 1].record()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    step_ms = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps))
     pd_ms, pd_launches, iters_per_launch = vfs.profile_read(R, reset=True)
     vfs.profile_enable(R, False)
     log(f"bench: {args.steps} timed steps in {dt:.3f} s")
@@ -161,7 +167,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "frac_kind": "effective: 117 B per pixel-iteration x pixel-iterations per launch",
                 "kernel": f"level-0 primal-dual pass ({iters_per_launch} iterations of Eq. (11) per launch, "
-                          f"{'pd2_kernel' if iters_per_launch == 2 else 'pdn_kernel'}<TGV>)",
+                          f"pdn_kernel<TGV>)",
                 "iters_per_launch": iters_per_launch,
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": pd_launches,
                 "textbook_bytes_per_launch": textbook_bytes,
@@ -238,6 +244,8 @@ def main():
     line = {
         "metric": "primal-dual Mpix-iter/s", "value": round(value, 1), "unit": "Mpix-iter/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
+        "step_ms": {"median": round(float(np.median(step_ms)), 2), "p10": round(float(np.percentile(step_ms, 10)), 2),
+                    "p90": round(float(np.percentile(step_ms, 90)), 2)},
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded rendered fisheye rooms)",
         "config": {"workload": f"{args.config} {cfg['name']}: {n} x {W}x{H} {cfg['model']} {cfg['fov_deg']:.0f}deg, "
