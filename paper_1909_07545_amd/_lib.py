@@ -309,13 +309,19 @@ def step_linearise(J0, J1, gamma, flags, u, u_w, w, gamma_w, tpack, rho, clip: b
                                     float(du_max), _stream(stream)))
 
 
-def step_pd(tpack, rho, flags, u, v, p, q, params: dict, iters: int, stream=None):
-    H, W = u.shape
+def step_pd(tpack, rho, flags, u, v, p, q, params: dict, iters: int, stream=None, width=None, height=None):
+    """vfs_step_pd on (rows, pitch[, c]) planes; width / height (default: the
+    planes' pitch and row count) give the image inside them."""
+    rows, pitch = u.shape
+    W = pitch if width is None else int(width)
+    H = rows if height is None else int(height)
+    if not (0 < W <= pitch and 0 < H <= rows):
+        raise ValueError("step_pd: width / height outside the planes")
     su, sp = torch.empty_like(u), torch.empty_like(p)
     sv = torch.empty_like(v) if v is not None else None
     sq = torch.empty_like(q) if q is not None else None
     pp = _params(params)
-    _check(lib().vfs_step_pd(W, H, W, _ptr(tpack), _ptr(rho), _ptr(flags), _ptr(u), _ptr(v), _ptr(p), _ptr(q),
+    _check(lib().vfs_step_pd(W, H, pitch, _ptr(tpack), _ptr(rho), _ptr(flags), _ptr(u), _ptr(v), _ptr(p), _ptr(q),
                              _ptr(su), _ptr(sv), _ptr(sp), _ptr(sq), ctypes.byref(pp), int(iters),
                              _stream(stream)))
 

@@ -209,7 +209,8 @@ def _pd_state(cid, level, tgv=True, seed=5):
     ("c1", 1, 30, "tgv", 0.3, 0), ("c2", 0, 20, "tgv", 0.0, 0), ("c5", 0, 3, "tgv", 0.0, 0),
     ("c1", 0, 50, "tgv", 0.0, 3), ("r200", 0, 8, "tv", 0.0, 3), ("r200", 1, 11, "tgv", 0.4, 3),
     ("c5", 0, 8, "tgv", 0.0, 3), ("c1", 0, 50, "tgv", 0.0, 4), ("r200", 0, 9, "tgv", 0.0, 4),
-    ("r200", 0, 6, "tv", 0.0, 4), ("c2", 0, 14, "tgv", 0.0, 4), ("c5", 0, 6, "tgv", 0.0, 2)])
+    ("r200", 0, 6, "tv", 0.0, 4), ("c2", 0, 14, "tgv", 0.0, 4), ("c5", 0, 6, "tgv", 0.0, 2),
+    ("c5", 0, 4, "tgv", 0.0, 0), ("r200", 0, 3, "tgv", 0.3, 3), ("r200", 0, 2, "tgv", 0.0, 2)])
 def test_primal_dual(vfs, cid, level, K, reg, tg, npass):
     """K iterations of Eq. (11) from a warp start: u, v, p, q within 2e-5 of
     the FP64 oracle (float32 accumulates ~1e-7 per iteration).  npass: the
@@ -293,6 +294,57 @@ def test_primal_dual_16bit_storage(vfs, cid, level, K, reg, storage, npass):
         d = np.abs(g - st[k])[inside]
         print(cid, level, K, reg, storage, npass, k, float(d.mean()), float(d.max()), mean_bar, max_bar, flush=True)
         assert d.max() <= max_bar and d.mean() <= mean_bar, (k, float(d.mean()), float(d.max()))
+
+
+@pytest.mark.parametrize("storage,npass,K", [(0, 2, 7), (0, 3, 8), (0, 4, 9), (0, 4, 3), (1, 3, 8), (2, 4, 6)])
+def test_primal_dual_reads_nothing_outside_the_image(vfs, storage, npass, K):
+    """The pass kernels address a row through a buffer resource whose record
+    count is the image width, and give rows outside the image a count of 0.
+    A ragged 201 x 150 image in planes of 256-element rows with 6 rows below
+    it: with NaN in every float (and every flag bit set) outside the image,
+    each output inside the image is bitwise what it is with zeros there, and
+    finite -- the kernels read nothing outside the image.  Pass depths 2, 3,
+    4, with and without the first pass of a warp, FP32 and 16-bit storage."""
+    import torch
+    H, W, P, extra = 150, 201, 256, 6
+    rng = np.random.default_rng(11)
+    yy, xx = np.mgrid[0:H, 0:W]
+    m = ((xx - 100.0) ** 2 + (yy - 74.5) ** 2 <= 72.0 ** 2).astype(np.uint8)
+    mx = np.zeros_like(m)
+    mx[:, :-1] = m[:, :-1] & m[:, 1:]
+    my = np.zeros_like(m)
+    my[:-1] = m[:-1] & m[1:]
+    data = m & (rng.random((H, W)) < 0.9)
+    flags = (m | (mx << 1) | (my << 2) | (data << 3)).astype(np.uint8)
+    J0 = _smooth_image(H, W, 3)
+    T = oracle.tensor(f32(J0), m, 9.0, 0.85).astype(np.float32)
+    Iu = (rng.normal(0, 0.05, (H, W)) * data).astype(np.float32)
+    rho = (rng.normal(0, 0.05, (H, W)) * data).astype(np.float32)
+    u = (1.5 + 0.3 * rng.random((H, W))).astype(np.float32)
+    v = (0.05 * rng.normal(size=(H, W, 2)) * m[..., None]).astype(np.float32)
+    p = (oracle.project_balls(0.7 * rng.normal(size=(H, W, 2)), 2).reshape(H, W, 2) * m[..., None]).astype(np.float32)
+    q = (oracle.project_balls(0.7 * rng.normal(size=(H, W, 4)), 4).reshape(H, W, 4) * m[..., None]).astype(np.float32)
+    tpack = np.concatenate([T, Iu[..., None]], -1).astype(np.float32)
+    dt = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}[storage]
+    params = dict(configs.PAPER_PARAMS, levels=1, warps=1, iters=K, reg="tgv", storage=storage, pass_iters=npass)
+
+    def run(fill):
+        def plane(a, dtype, fill_value):
+            shape = (H + extra, P) + a.shape[2:]
+            t = torch.full(shape, fill_value, dtype=dtype, device="cuda")
+            t[:H, :W] = torch.from_numpy(a).to(dtype).cuda()
+            return t
+        f = plane(flags, torch.uint8, 255 if fill else 0)
+        nan = float("nan") if fill else 0.0
+        st = dict(tpack=plane(tpack, dt, nan), rho=plane(rho, torch.float32, nan), u=plane(u, torch.float32, nan),
+                  v=plane(v, torch.float32, nan), p=plane(p, dt, nan), q=plane(q, dt, nan))
+        vfs.step_pd(st["tpack"], st["rho"], f, st["u"], st["v"], st["p"], st["q"], params, K, width=W, height=H)
+        torch.cuda.synchronize()
+        return {k: st[k][:H, :W].float().cpu() for k in ("u", "v", "p", "q")}
+
+    clean, dirty = run(False), run(True)
+    for k in clean:
+        assert torch.isfinite(clean[k]).all() and torch.equal(clean[k], dirty[k]), k
 
 
 @pytest.mark.parametrize("cid,level", [("c1", 1), ("r200", 1), ("c5", 1)])
