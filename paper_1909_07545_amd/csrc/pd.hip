@@ -64,18 +64,19 @@ constexpr int kCols = kLanes - 2;    // owned columns per wavefront, one-iterati
 // idles the chip); launches too small to fill the SIMDs go shorter
 // (short_march_floor).
 constexpr int kBY = 16;
-// The 16-bit three-iteration kernel is bound by vector issue rather than by
-// memory: its marches aim at 28 rows, which re-compute fewer halo rows
-// (measured on 8 pairs of 2048x2048: 552 us per launch at 16 rows, 517 at
-// 28, 520 at 36; FP32 is slower beyond 16: 677, 685 at 22, 693 at 28).
+// The 16-bit kernels are bound by vector issue rather than by memory: their
+// marches aim at 28 rows, which re-compute fewer halo rows (measured on 8
+// pairs of 2048x2048, three iterations per pass: 552 us per launch at 16
+// rows, 517 at 28, 520 at 36; the FP32 three-iteration pass is slower beyond
+// 16: 677, 685 at 22, 693 at 28).
 constexpr int kBY16 = 28;
-// The FP32 four-iteration kernel is issue-bound too: its marches aim at 40
-// rows (measured on 8 pairs of 2048x2048 with carried step-size bases, three
-// wavefronts per SIMD: 735 us per launch at a 24-row target, 726 at 32, 719
-// at 40 -- 41-row marches in five rounds; without carried bases, four
-// wavefronts per SIMD: 817 us at 16, 779 at 24, 770 at 32).  A target that
-// leaves fewer than kRoundsForShort rounds falls back to one round of long
-// marches.
+// The FP32 four-iteration kernel spends more vector issue per row than the
+// three-iteration one reads bytes: its marches aim at 40 rows (measured on 8
+// pairs of 2048x2048 with carried step-size bases, three wavefronts per
+// SIMD: 735 us per launch at a 24-row target, 726 at 32, 719 at 40 -- 41-row
+// marches in five rounds; without carried bases, four wavefronts per SIMD:
+// 817 us at 16, 779 at 24, 770 at 32).  A target that leaves fewer than
+// kRoundsForShort rounds falls back to one round of long marches.
 constexpr int kBY4 = 40;
 constexpr int kBYs = 4;
 constexpr long long kRoundsForShort = 4;
