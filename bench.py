@@ -305,7 +305,7 @@ def serving_study(args, log_prefix="serving"):
     handles = {(r, s): vfs.Rig(rg["cam0"], rg["cam1"], rg["R"], rg["t"], rg["levels"])
                for r, per in enumerate(rigs) for s, rg in enumerate(per)}
     imgs = {k: (torch.from_numpy(v[0][0]).cuda(), torch.from_numpy(v[0][1]).cuda()) for k, v in pool.items()}
-    base = configs.solver_params(dict(levels=1, warps=sp["warps"], iters=sp["iters"]))
+    base = configs.solver_params(dict(levels=1, warps=sp["warps"], iters=sp["iters"]), pass_iters=args.pass_iters)
     p32, p16 = dict(base, storage=0), dict(base, storage=1)
     n = args.serve_requests
     trace0 = serving.make_trace(1.0, n, sp)

@@ -102,7 +102,7 @@ typedef struct {
     int storage;               /* vfs_storage */
     int pass_iters;            /* primal-dual iterations per pass over memory of the dominant launches:
                                   0 = chosen by the library from the pair size and storage (from 2 M
-                                  level-0 pixels: 4 in FP32, 3 with 16-bit storage; else 2), or 2,
+                                  level-0 pixels: 4 in FP32, 3 with 16-bit storage; else 3), or 2,
                                   3, 4; the choice changes only the rounding points of 16-bit
                                   storage and the speed */
     int data_term;             /* vfs_data_term */

@@ -256,20 +256,21 @@ vfs_status check_params(const vfs_params* p)
 
 // Iterations per pass of the dominant primal-dual launches for pairs whose
 // level 0 is g's, in a storage mode, unless `requested` (2, 3 or 4) fixes it.
-// Measured on MI355X (8 pairs of 2048x2048, whole solve): on these pairs
-// four iterations per pass in FP32 (157.5 Gpix-iter/s against 133.2 with
-// three; an earlier build 138.3 against 131.0) and three with 16-bit storage
-// (171.6 against 156.5 with four: the 16-bit kernels spend more of their
-// vector issue per iteration, and a fourth iteration adds halo work); two
-// where the launches are latency-bound (pairs up to 1280x1024, alone or in serving
-// buckets).  The choice depends on the pair's size and the storage only, not
-// on how many pairs share a launch, so that a pair's result does not depend
-// on its batch (16-bit storage rounds the duals at pass boundaries; in FP32
-// the pass depth changes no result).
+// Measured on MI355X, whole solves: four iterations per pass in FP32 from
+// 2 M level-0 pixels (8 pairs of 2048x2048: 165.3 Gpix-iter/s against 134.6
+// with three), three with 16-bit storage there (171.6 against 162.6 with
+// four: the 16-bit kernels spend more vector issue per iteration), and three
+// on smaller pairs in both modes, where the launches are latency-bound and
+// fewer of them per warp pays (1280x1024: 55.6 against 50.0 with two and 52.6
+// with four; 640x480: 19.6 against 18.6 and 18.6; the serving study: 386
+// against 364 pairs/s with two).  The choice depends on the pair's size and
+// the storage only, not on how many pairs share a launch, so that a pair's
+// result does not depend on its batch (16-bit storage rounds the duals at
+// pass boundaries; in FP32 the pass depth changes no result).
 int pd_pass_iters(const Geometry& g, int requested, int storage)
 {
     if (requested >= 2 && requested <= 4) return requested;
-    if ((long long)g.W[0] * g.H[0] < (2ll << 20)) return 2;
+    if ((long long)g.W[0] * g.H[0] < (2ll << 20)) return 3;
     return storage == VFS_F32 ? 4 : 3;
 }
 

@@ -1,7 +1,7 @@
 """Accuracy studies against full FP64 oracle solves (a script, not collected
 by pytest; it needs a GPU and a few minutes of host CPU).
 
-  python -m tests.accuracy_study precision OUT.json
+  python -m tests.accuracy_study precision OUT.json [c3,c5]
       FP32 / FP16 / BF16 storage of one 1280x1024 190-degree pair (6 levels x
       10 warps x 150 iterations) and of pair 0 of the 2048x2048 200-degree
       batch (7 x 15 x 200): displacement and depth error against the oracle,
@@ -70,7 +70,7 @@ def precision():
     from synth import configs, scene
 
     table = {}
-    for cid in ("c3", "c5"):
+    for cid in (sys.argv[3].split(",") if len(sys.argv) > 3 else ("c3", "c5")):
         cfg = configs.get(cid)
         params = configs.solver_params(cfg)
         rig = scene.make_rig(cfg)

@@ -215,7 +215,7 @@ def test_primal_dual(vfs, cid, level, K, reg, tg, npass):
     """K iterations of Eq. (11) from a warp start: u, v, p, q within 2e-5 of
     the FP64 oracle (float32 accumulates ~1e-7 per iteration).  npass: the
     iterations per pass of the multi-iteration launches (0: the library's
-    choice, 4 on the 2048x2048 level, 2 on smaller pairs), so that the 2-, 3-
+    choice, 4 on the 2048x2048 level, 3 on smaller pairs), so that the 2-, 3-
     and 4-iteration kernels all run, with the first pass of a warp (K >= N,
     its first iteration the dual half alone) and without it (K < N starts with
     a dual-only launch), and with the remainders of K - N that need one- and
