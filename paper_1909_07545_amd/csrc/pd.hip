@@ -751,11 +751,14 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
     const int r_lo = y0 - (N - 1), r_hi = y1 + 2 * N - 2, r_load = y1 + N - 1;
     const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
     // PF: the next step's row is read one step ahead, into the other slot,
-    // where the registers allow it without losing a wavefront per SIMD (the
-    // four-iteration kernels: 168 VGPRs in FP32, three wavefronts per SIMD;
+    // where the registers allow it without losing a wavefront per SIMD: the
+    // four-iteration kernels (168 VGPRs in FP32, three wavefronts per SIMD;
     // measured on 8 pairs of 2048x2048: 720 -> 706 us per launch with the
-    // prefetch in both marches)
-    constexpr bool PF = N >= 4;
+    // prefetch in both marches) and the FP32 three-iteration kernel, which
+    // runs three wavefronts per SIMD without it too (133 -> 150 VGPRs; whole
+    // solves of a 1280x1024 pair 55.7 -> 58.3 Gpix-iter/s, 640x480 19.6 ->
+    // 20.8).  The 16-bit three-iteration kernel would drop to three.
+    constexpr bool PF = N >= 4 || (N == 3 && S == ST_F32);
     Row rw[2];
     if constexpr (PF) {
         rw[0] = read_row<TGV, true, S>(P, x, r_lo);
@@ -910,8 +913,8 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
     rw[0] = zero_row();
     rw[1] = read_row<TGV, true, S>(P, x, r_hi);
     // PFU: the row above the next step's row is read one step ahead too (in
-    // the four-iteration kernels, as in march_down)
-    constexpr bool PFU = N >= 4;
+    // the kernels that prefetch in march_down)
+    constexpr bool PFU = N >= 4 || (N == 3 && S == ST_F32);
     Row pf;
     if constexpr (PFU) pf = read_row<TGV, true, S>(P, x, r_hi - 1);
     auto step = [&](const int r, auto par) {
@@ -1010,7 +1013,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
 // on the same inputs, so each pixel's result does not depend on the
 // direction (this file contracts multiply-adds only within one expression).
 template <bool TGV, int S, int N, bool FIRST>
-__global__ __launch_bounds__(kLanes * kWaves, N == 4 ? 3 : (S != ST_F32 ? 4 : 1)) void pdn_kernel(PdArgs a, int by,
+__global__ __launch_bounds__(kLanes * kWaves, N == 4 || (N == 3 && S == ST_F32) ? 3 : (S != ST_F32 ? 4 : 1)) void pdn_kernel(PdArgs a, int by,
                                                                                                int segs)
 {
     constexpr int kColsN = kLanes - 2 * N;
