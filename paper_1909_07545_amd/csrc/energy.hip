@@ -117,7 +117,7 @@ __global__ void finish_kernel(const double* in, long long n, int use_max, double
     for (long long k = threadIdx.x; k < n; k += 256) x = use_max ? fmax(x, p[k]) : x + p[k];
     part[threadIdx.x] = x;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (unsigned s = 128; s > 0; s >>= 1) {
         if (threadIdx.x < s)
             part[threadIdx.x] = use_max ? fmax(part[threadIdx.x], part[threadIdx.x + s])
                                         : part[threadIdx.x] + part[threadIdx.x + s];
