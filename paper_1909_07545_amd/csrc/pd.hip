@@ -173,6 +173,8 @@ constexpr int kRsrcWord3 = 0x00020000;   // untyped 32-bit data, no swizzle, no 
 // the column offset of a lane that writes nothing: times 4, 8 or 16 bytes it
 // is 2^29, 2^30 or 2^31, past any row's records
 constexpr uint32_t kNoColumn = 0x08000000u;
+// cache policy of a store that the next read will not find in any cache (non-temporal)
+constexpr int kStoreNT = 2;
 
 __device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void* plane, long long row, int pitch, int elem, int bytes)
 {
@@ -244,38 +246,70 @@ __device__ inline Row read_row(const Planes& P, int x, int r, bool valid = true)
 }
 
 // Writes of row r's results by the owner lanes (xs: the lane's column, or
-// a column past any row for the other lanes).
-template <bool TGV>
-__device__ inline void write_primal(const Planes& P, uint32_t xs, int r, float un, float2 vn)
+// a column past any row for the other lanes); with NT non-temporally.
+template <int POLICY>
+__device__ inline void store_b32(uint32_t v, __amdgpu_buffer_rsrc_t rs, uint32_t off)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(un), row_rsrc(P.u_out, r, P.pitch, 4, P.W * 4), xs * 4u, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(v, rs, off, 0, POLICY);
+}
+template <int POLICY>
+__device__ inline void store_b64(__attribute__((ext_vector_type(2))) uint32_t v, __amdgpu_buffer_rsrc_t rs,
+                                 uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(v, rs, off, 0, POLICY);
+}
+template <int POLICY>
+__device__ inline void store_b128(__attribute__((ext_vector_type(4))) uint32_t v, __amdgpu_buffer_rsrc_t rs,
+                                  uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, POLICY);
+}
+
+template <bool TGV, int POLICY>
+__device__ inline void write_primal_p(const Planes& P, uint32_t xs, int r, float un, float2 vn)
+{
+    store_b32<POLICY>(__float_as_uint(un), row_rsrc(P.u_out, r, P.pitch, 4, P.W * 4), xs * 4u);
     if (TGV) {
         const __attribute__((ext_vector_type(2))) uint32_t v = {__float_as_uint(vn.x), __float_as_uint(vn.y)};
-        __builtin_amdgcn_raw_buffer_store_b64(v, row_rsrc(P.v_out, r, P.pitch, 8, P.W * 8), xs * 8u, 0, 0);
+        store_b64<POLICY>(v, row_rsrc(P.v_out, r, P.pitch, 8, P.W * 8), xs * 8u);
     }
 }
 
-template <bool TGV, int S>
-__device__ inline void write_dual(const Planes& P, uint32_t xs, int r, float2 pn, float4 qn)
+template <bool TGV, int S, int POLICY>
+__device__ inline void write_dual_p(const Planes& P, uint32_t xs, int r, float2 pn, float4 qn)
 {
     if constexpr (S == ST_F32) {
         const __attribute__((ext_vector_type(2))) uint32_t pv = {__float_as_uint(pn.x), __float_as_uint(pn.y)};
-        __builtin_amdgcn_raw_buffer_store_b64(pv, row_rsrc(P.p_out, r, P.pitch, 8, P.W * 8), xs * 8u, 0, 0);
+        store_b64<POLICY>(pv, row_rsrc(P.p_out, r, P.pitch, 8, P.W * 8), xs * 8u);
         if (TGV) {
             const __attribute__((ext_vector_type(4))) uint32_t qv = {__float_as_uint(qn.x), __float_as_uint(qn.y),
                                                                      __float_as_uint(qn.z), __float_as_uint(qn.w)};
-            __builtin_amdgcn_raw_buffer_store_b128(qv, row_rsrc(P.q_out, r, P.pitch, 16, P.W * 16), xs * 16u, 0, 0);
+            store_b128<POLICY>(qv, row_rsrc(P.q_out, r, P.pitch, 16, P.W * 16), xs * 16u);
         }
     } else {
         const uint32_t pv = uint32_t(enc16<S>(pn.x)) | (uint32_t(enc16<S>(pn.y)) << 16);
-        __builtin_amdgcn_raw_buffer_store_b32(pv, row_rsrc(P.p_out, r, P.pitch, 4, P.W * 4), xs * 4u, 0, 0);
+        store_b32<POLICY>(pv, row_rsrc(P.p_out, r, P.pitch, 4, P.W * 4), xs * 4u);
         if (TGV) {
             const __attribute__((ext_vector_type(2))) uint32_t qv = {
                 uint32_t(enc16<S>(qn.x)) | (uint32_t(enc16<S>(qn.y)) << 16),
                 uint32_t(enc16<S>(qn.z)) | (uint32_t(enc16<S>(qn.w)) << 16)};
-            __builtin_amdgcn_raw_buffer_store_b64(qv, row_rsrc(P.q_out, r, P.pitch, 8, P.W * 8), xs * 8u, 0, 0);
+            store_b64<POLICY>(qv, row_rsrc(P.q_out, r, P.pitch, 8, P.W * 8), xs * 8u);
         }
     }
+}
+
+template <bool TGV>
+__device__ inline void write_primal(const Planes& P, uint32_t xs, int r, float un, float2 vn, bool nt = false)
+{
+    if (nt) write_primal_p<TGV, kStoreNT>(P, xs, r, un, vn);
+    else write_primal_p<TGV, 0>(P, xs, r, un, vn);
+}
+
+template <bool TGV, int S>
+__device__ inline void write_dual(const Planes& P, uint32_t xs, int r, float2 pn, float4 qn, bool nt = false)
+{
+    if (nt) write_dual_p<TGV, S, kStoreNT>(P, xs, r, pn, qn);
+    else write_dual_p<TGV, S, 0>(P, xs, r, pn, qn);
 }
 
 // A flag bit as the float 0 or 1 that multiplies a masked difference: a
@@ -750,6 +784,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
     }
     const int r_lo = y0 - (N - 1), r_hi = y1 + 2 * N - 2, r_load = y1 + N - 1;
     const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
+    const bool nt = S == ST_F32 && a.nt_stores;
     // PF: the next step's row is read one step ahead, into the other slot,
     // where the registers allow it without losing a wavefront per SIMD: the
     // four-iteration kernels (168 VGPRs in FP32, three wavefronts per SIMD;
@@ -821,7 +856,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
             const float th = a.theta_n[i];
             const float ubn = un + th * (un - u_in);
             const float2 vbn = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
-            if (i == N - 1 && pr >= y0 && pr < y1) write_primal<TGV>(P, xs, pr, un, vn);
+            if (i == N - 1 && pr >= y0 && pr < y1) write_primal<TGV>(P, xs, pr, un, vn, nt);
             // dual step of iteration i at row r - 2i - 1 (inside its rows
             // whenever the row below is, save the first)
             const int dr = pr - 1;
@@ -838,7 +873,7 @@ __device__ __forceinline__ void march_down(const PdArgs& a, const Planes& P, int
                 else
                     dual_at<TGV>(py, qy, t_ab, flag(2 * i + 1), xbu[i], xbv[i], ub_r, vb_r, ubn, vbn, a0, a1,
                                  a.sigma_n[i], sqn[i], pn, qn);
-                if (i == N - 1 && dr >= y0 && dr < y1) write_dual<TGV, S>(P, xs, dr, pn, qn);
+                if (i == N - 1 && dr >= y0 && dr < y1) write_dual<TGV, S>(P, xs, dr, pn, qn, nt);
                 yp[i][s] = pn;
                 yq[i][s] = qn;
             }
@@ -907,6 +942,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
     }
     const int r_hi = y1 + N - 1, r_lo = y0 - (N - 1);
     const uint32_t xs = owner ? uint32_t(x) : kNoColumn;
+    const bool nt = S == ST_F32 && a.nt_stores;
     // the current row and the row above it, in slots as above: the row above
     // of one step is the current row of the next
     Row rw[2];
@@ -977,7 +1013,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
                 const float th = a.theta_n[i];
                 ub = un + th * (un - u_in);
                 vb = make_float2(vn.x + th * (vn.x - v_in.x), vn.y + th * (vn.y - v_in.y));
-                if (i == N - 1 && q >= y0 && q < y1) write_primal<TGV>(P, xs, q, un, vn);
+                if (i == N - 1 && q >= y0 && q < y1) write_primal<TGV>(P, xs, q, un, vn, nt);
             }
             xu[i][s] = un;
             xv[i][s] = vn;
@@ -994,7 +1030,7 @@ __device__ __forceinline__ void march_up(const PdArgs& a, const Planes& P, int x
                 else
                     dual_at<TGV>(p_in, q_in, t_q, flag(i), ub, vb, ub_r, vb_r, xbu[i][o], xbv[i][o], a0, a1,
                                  a.sigma_n[i], sqn[i], pn, qn);
-                if (i == N - 1 && q >= y0 && q < y1) write_dual<TGV, S>(P, xs, q, pn, qn);
+                if (i == N - 1 && q >= y0 && q < y1) write_dual<TGV, S>(P, xs, q, pn, qn, nt);
             }
             yp[i][s] = pn;
             yq[i][s] = qn;
@@ -1140,9 +1176,21 @@ void launch_mode(const PdArgs& a, hipStream_t s)
         hipLaunchKernelGGL((pd_kernel<MODE, TGV, S>), dim3(m.blocks), dim3(kLanes * kWaves), 0, s, a, m.by, m.segs);
 }
 
+// Bytes above which a multi-iteration pass's state cannot stay in the last
+// level cache between passes (the 256 MB Infinity Cache of MI355X): its FP32
+// passes then store it non-temporally, keeping L2 for the halo rows and
+// columns that neighbouring marches re-read (measured on 8 pairs of
+// 2048x2048: 700.0 -> 697.1 us per level-0 launch; with non-temporal stores
+// everywhere, a cache-resident 1280x1024 pair went 31.2 -> 34.2 us and
+// 16-bit storage on the 2048x2048 pairs 503 -> 540 us, so neither gets them).
+constexpr long long kLastLevelCache = 256ll << 20;
+
 template <bool TGV, int S, int N, bool FIRST>
-void launch_fusedn(const PdArgs& a, hipStream_t s)
+void launch_fusedn(const PdArgs& a0, hipStream_t s)
 {
+    PdArgs a = a0;
+    const long long state = (long long)a.lc.n * a.lc.g.W[a.lc.gl] * a.lc.g.H[a.lc.gl] * 93;
+    a.nt_stores = S == ST_F32 && state > kLastLevelCache;
     const March m = march_shape(a, kLanes - 2 * N, pdn_kernel<TGV, S, N, FIRST>, short_march_floor(a, kLanes - 2 * N),
                                 S == ST_F32 ? (N == 4 ? kBY4 : kBY) : kBY16);
     if (m.blocks)

@@ -420,6 +420,7 @@ struct PdArgs {
     int tgv;                    // 1: TGV-L1 (Eq. (10)); 0: TV-L1 (v = 0, no q)
     int storage;                // Storage of p, q and the tensor pack
     int pass;                   // iterations per pass of the multi-iteration launches (2, 3, 4)
+    int nt_stores;              // set per launch: the multi-iteration pass writes its state non-temporally
 };
 void launch_pd(const PdArgs& a, hipStream_t s);
 // Queries the occupancy the primal-dual launches are sized by, for the
