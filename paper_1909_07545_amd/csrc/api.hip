@@ -258,8 +258,12 @@ vfs_status check_params(const vfs_params* p)
 // level 0 is g's, in a storage mode, unless `requested` (2, 3 or 4) fixes it.
 // Measured on MI355X, whole solves: four iterations per pass in FP32 from
 // 2 M level-0 pixels (8 pairs of 2048x2048: 165.3 Gpix-iter/s against 134.6
-// with three), three with 16-bit storage there (171.6 against 162.6 with
-// four: the 16-bit kernels spend more vector issue per iteration), and three
+// with three); three with 16-bit storage there (chosen at 171.6 against
+// 162.6 with four, the 16-bit kernels spending more vector issue per
+// iteration; since the first pass of a warp and the next-row prefetch, four
+// measure 0.6 % faster, kept at three because the 16-bit accuracy figures
+// were measured with it and a change of depth moves the points where the
+// duals are rounded); and three
 // on smaller pairs in both modes, where the launches are latency-bound and
 // fewer of them per warp pays (1280x1024: 55.6 against 50.0 with two and 52.6
 // with four; 640x480: 19.6 against 18.6 and 18.6; the serving study: 386
