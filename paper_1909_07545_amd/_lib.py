@@ -159,12 +159,62 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _dev_f32(t, shape=None):
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
-        raise TypeError("expected a contiguous float32 CUDA tensor")
-    if shape is not None and tuple(t.shape) != tuple(shape):
-        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+_F32, _U8 = (torch.float32,), (torch.uint8,)
+
+
+def _need(t, shape, dtypes, name, optional=False):
+    """t, checked: a contiguous CUDA tensor of one of ``dtypes`` and of this
+    shape (None passes when ``optional``).  The C ABI takes bare pointers
+    and the sizes given beside them, so these checks are what keeps its
+    kernels inside the caller's buffers."""
+    if t is None:
+        if optional:
+            return None
+        raise TypeError(f"{name}: a tensor is required")
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise TypeError(f"{name}: expected a contiguous CUDA tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {' or '.join(str(d) for d in dtypes)}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
     return t
+
+
+def _plane(t, name):
+    """(rows, columns) of a 2-D tensor argument that sets the others' sizes."""
+    if not (isinstance(t, torch.Tensor) and t.dim() == 2):
+        raise ValueError(f"{name}: expected a 2-D tensor")
+    return int(t.shape[0]), int(t.shape[1])
+
+
+def _batch_args(rig, I0s, I1s, betas, etas, out=None):
+    """Checks of a batch's images (one I0 and one I1 of the rig's size per
+    pair), per-pair tensor parameters and output tensors; returns n."""
+    n = len(I0s)
+    if len(I1s) != n:
+        raise ValueError(f"I1s: {len(I1s)} images for {n} pairs")
+    for name, seq in (("betas", betas), ("etas", etas)):
+        if seq is not None and len(seq) != n:
+            raise ValueError(f"{name}: {len(seq)} values for {n} pairs")
+    if out is not None and len(out) != n:
+        raise ValueError(f"out: {len(out)} entries for {n} pairs")
+    H, W = rig.height, rig.width
+    for k in range(n):
+        _need(I0s[k], (H, W), _F32, f"I0s[{k}]")
+        _need(I1s[k], (H, W), _F32, f"I1s[{k}]")
+    if out is not None:
+        for k, o in enumerate(out):
+            _outputs(o, H, W, f"out[{k}]", required=("u", "w", "depth", "z", "valid"))
+    return n
+
+
+def _outputs(o, H, W, name, required):
+    """Output tensors of one pair: u, depth, z (H, W) float32, w (H, W, 2)
+    float32, valid (H, W) uint8; the keys not in ``required`` may be absent."""
+    shapes = dict(u=((H, W), _F32), w=((H, W, 2), _F32), depth=((H, W), _F32), z=((H, W), _F32),
+                  valid=((H, W), _U8))
+    for k, (shape, dt) in shapes.items():
+        _need(o.get(k), shape, dt, f"{name}['{k}']", optional=k not in required)
 
 
 class Rig:
@@ -215,10 +265,8 @@ def solve_batch(rig: Rig, I0s, I1s, params: dict, betas=None, etas=None, stream=
     """Whole method on a batch of pairs (vfs_solve_batch).  Inputs: lists of
     (H, W) float32 CUDA tensors.  Returns a list of dicts of output tensors
     (u, w, depth, z, valid); ``out`` may pass pre-allocated ones."""
-    n = len(I0s)
+    n = _batch_args(rig, I0s, I1s, betas, etas, out)
     H, W = rig.height, rig.width
-    for t in list(I0s) + list(I1s):
-        _dev_f32(t, (H, W))
     if out is None:
         out = [dict(u=torch.empty((H, W), device="cuda"), w=torch.empty((H, W, 2), device="cuda"),
                     depth=torch.empty((H, W), device="cuda"), z=torch.empty((H, W), device="cuda"),
@@ -244,10 +292,8 @@ def solve_probe(rig: Rig, I0s, I1s, params: dict, level: int, warp: int, pair: i
     p, q, tpack, rho, gw (after the warp's linearisation), u_pd, v_pd, p_pd,
     q_pd (after its iterations) and u_next, w_next (after its clip); p, q and
     tpack in the storage dtype (float32, float16 or bfloat16)."""
-    n = len(I0s)
+    n = _batch_args(rig, I0s, I1s, betas, etas)
     H, W = rig.height, rig.width
-    for t in list(I0s) + list(I1s):
-        _dev_f32(t, (H, W))
     lv = min(max(int(level), 0), rig.levels - 1)   # plane sizes only: the library checks the level
     Hl, Wl = H >> lv, W >> lv
     sd = _STORAGE_DTYPE[int(params.get("storage", 0))]
@@ -276,10 +322,8 @@ def solve_batch_noalloc(rig: Rig, I0s, I1s, params: dict, out: list, betas=None,
     """vfs_solve_batch_noalloc: the batched solve with the library's fixed
     device scratch instead of an allocated workspace.  ``out``: one dict of
     pre-allocated output tensors (u, w, depth, z, valid) per pair."""
-    n = len(I0s)
-    H, W = rig.height, rig.width
-    for t in list(I0s) + list(I1s):
-        _dev_f32(t, (H, W))
+    n = _batch_args(rig, I0s, I1s, betas, etas, out)
+    W = rig.width
     arr = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])  # noqa: E731
     p = _params(params)
     bet = (ctypes.c_double * n)(*betas) if betas is not None else None
@@ -296,14 +340,21 @@ def solve(rig: Rig, I0, I1, params: dict, stream=None):
 
 
 def step_tensor(J0, flags, beta: float, eta: float, tpack, stream=None):
-    H, W = J0.shape
+    H, W = _plane(J0, "J0")
+    _need(J0, (H, W), _F32, "J0")
+    _need(flags, (H, W), _U8, "flags")
+    _need(tpack, (H, W, 4), _F32, "tpack")
     _check(lib().vfs_step_tensor(W, H, W, _ptr(J0), _ptr(flags), float(beta), float(eta), _ptr(tpack),
                                  _stream(stream)))
 
 
 def step_linearise(J0, J1, gamma, flags, u, u_w, w, gamma_w, tpack, rho, clip: bool, clip_only: bool,
                    du_max: float, stream=None):
-    H, W = J0.shape
+    H, W = _plane(J0, "J0")
+    for name, t, c, dt in (("J0", J0, 1, _F32), ("J1", J1, 1, _F32), ("gamma", gamma, 2, _F32),
+                           ("flags", flags, 1, _U8), ("u", u, 1, _F32), ("u_w", u_w, 1, _F32), ("w", w, 2, _F32),
+                           ("gamma_w", gamma_w, 2, _F32), ("tpack", tpack, 4, _F32), ("rho", rho, 1, _F32)):
+        _need(t, (H, W) if c == 1 else (H, W, c), dt, name)
     _check(lib().vfs_step_linearise(W, H, W, _ptr(J0), _ptr(J1), _ptr(gamma), _ptr(flags), _ptr(u), _ptr(u_w),
                                     _ptr(w), _ptr(gamma_w), _ptr(tpack), _ptr(rho), int(clip), int(clip_only),
                                     float(du_max), _stream(stream)))
@@ -312,11 +363,12 @@ def step_linearise(J0, J1, gamma, flags, u, u_w, w, gamma_w, tpack, rho, clip: b
 def step_pd(tpack, rho, flags, u, v, p, q, params: dict, iters: int, stream=None, width=None, height=None):
     """vfs_step_pd on (rows, pitch[, c]) planes; width / height (default: the
     planes' pitch and row count) give the image inside them."""
-    rows, pitch = u.shape
+    rows, pitch = _plane(u, "u")
     W = pitch if width is None else int(width)
     H = rows if height is None else int(height)
     if not (0 < W <= pitch and 0 < H <= rows):
         raise ValueError("step_pd: width / height outside the planes")
+    _state_args(tpack, rho, flags, u, v, p, q, rows, pitch, _STORAGE_DTYPE[int(params.get("storage", 0))])
     su, sp = torch.empty_like(u), torch.empty_like(p)
     sv = torch.empty_like(v) if v is not None else None
     sq = torch.empty_like(q) if q is not None else None
@@ -326,21 +378,43 @@ def step_pd(tpack, rho, flags, u, v, p, q, params: dict, iters: int, stream=None
                              _stream(stream)))
 
 
+def _state_args(tpack, rho, flags, u, v, p, q, rows, pitch, sd):
+    """The primal-dual state's planes (rows x pitch): u, rho float32, flags
+    uint8, v (2) float32, p (2), q (4) and tpack (4) in the storage dtype sd;
+    v and q may be None (TV-L1)."""
+    _need(tpack, (rows, pitch, 4), (sd,), "tpack")
+    _need(rho, (rows, pitch), _F32, "rho")
+    _need(flags, (rows, pitch), _U8, "flags")
+    _need(u, (rows, pitch), _F32, "u")
+    _need(v, (rows, pitch, 2), _F32, "v", optional=True)
+    _need(p, (rows, pitch, 2), (sd,), "p")
+    _need(q, (rows, pitch, 4), (sd,), "q", optional=True)
+
+
 def step_rank(I0, I1, R0, R1, stream=None):
     """Rank transforms of two (H, W) planes into R0, R1 (vfs_step_rank)."""
-    H, W = I0.shape
+    H, W = _plane(I0, "I0")
+    for name, t in (("I0", I0), ("I1", I1), ("R0", R0), ("R1", R1)):
+        _need(t, (H, W), _F32, name)
     _check(lib().vfs_step_rank(W, H, W, _ptr(I0), _ptr(I1), _ptr(R0), _ptr(R1), _stream(stream)))
 
 
 def step_gradient(I0, I1, G0, G1, stream=None):
     """Gradient magnitudes of two (H, W) planes into G0, G1 (vfs_step_gradient)."""
-    H, W = I0.shape
+    H, W = _plane(I0, "I0")
+    for name, t in (("I0", I0), ("I1", I1), ("G0", G0), ("G1", G1)):
+        _need(t, (H, W), _F32, name)
     _check(lib().vfs_step_gradient(W, H, W, _ptr(I0), _ptr(I1), _ptr(G0), _ptr(G1), _stream(stream)))
 
 
 def step_energy(tpack, rho, flags, u, v, params: dict, stream=None) -> float:
     """Linearised energy of Eq. (10) of the state (u, v) (vfs_step_energy)."""
-    H, W = u.shape
+    H, W = _plane(u, "u")
+    _need(tpack, (H, W, 4), _F32, "tpack")
+    _need(rho, (H, W), _F32, "rho")
+    _need(flags, (H, W), _U8, "flags")
+    _need(u, (H, W), _F32, "u")
+    _need(v, (H, W, 2), _F32, "v", optional=True)
     e = ctypes.c_double()
     pp = _params(params)
     _check(lib().vfs_step_energy(W, H, W, _ptr(tpack), _ptr(rho), _ptr(flags), _ptr(u), _ptr(v), ctypes.byref(pp),
@@ -351,7 +425,8 @@ def step_energy(tpack, rho, flags, u, v, params: dict, stream=None) -> float:
 def step_pd_energy(tpack, rho, flags, u, v, p, q, params: dict, iters: int, stream=None):
     """vfs_step_pd with the energy of every primal iterate: returns the
     (iters + 1,) energies E(x^0) .. E(x^iters)."""
-    H, W = u.shape
+    H, W = _plane(u, "u")
+    _state_args(tpack, rho, flags, u, v, p, q, H, W, torch.float32)
     su, sp = torch.empty_like(u), torch.empty_like(p)
     sv = torch.empty_like(v) if v is not None else None
     sq = torch.empty_like(q) if q is not None else None
@@ -365,7 +440,10 @@ def step_pd_energy(tpack, rho, flags, u, v, p, q, params: dict, iters: int, stre
 
 def diff_stats(a, b, flags=None, stream=None):
     """(mean, max, count) of |a - b| over flags bit 0 (all pixels if None)."""
-    H, W = a.shape
+    H, W = _plane(a, "a")
+    _need(a, (H, W), _F32, "a")
+    _need(b, (H, W), _F32, "b")
+    _need(flags, (H, W), _U8, "flags", optional=True)
     mean, mx, cnt = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
     _check(lib().vfs_diff_stats(W, H, W, _ptr(a), _ptr(b), _ptr(flags), ctypes.byref(mean), ctypes.byref(mx),
                                 ctypes.byref(cnt), _stream(stream)))
@@ -373,12 +451,23 @@ def diff_stats(a, b, flags=None, stream=None):
 
 
 def step_upsample(flags_c, u_c, w_c, u_f, w_f, stream=None):
-    Hc, Wc = u_c.shape
+    """(u, w) of a coarse level (Hc, Wc) to the fine planes (2 Hc, 2 Wc)."""
+    Hc, Wc = _plane(u_c, "u_c")
+    _need(flags_c, (Hc, Wc), _U8, "flags_c")
+    _need(u_c, (Hc, Wc), _F32, "u_c")
+    _need(w_c, (Hc, Wc, 2), _F32, "w_c")
+    _need(u_f, (2 * Hc, 2 * Wc), _F32, "u_f")
+    _need(w_f, (2 * Hc, 2 * Wc, 2), _F32, "w_f")
     _check(lib().vfs_step_upsample(Wc, Hc, Wc, _ptr(flags_c), _ptr(u_c), _ptr(w_c), 2 * Wc, _ptr(u_f), _ptr(w_f),
                                    _stream(stream)))
 
 
 def step_triangulate(rig: Rig, w, depth, z=None, valid=None, stream=None):
+    H, W = rig.height, rig.width
+    _need(w, (H, W, 2), _F32, "w")
+    _need(depth, (H, W), _F32, "depth")
+    _need(z, (H, W), _F32, "z", optional=True)
+    _need(valid, (H, W), _U8, "valid", optional=True)
     _check(lib().vfs_step_triangulate(rig.handle, rig.width, _ptr(w), _ptr(depth), _ptr(z), _ptr(valid),
                                       _stream(stream)))
 
@@ -452,9 +541,9 @@ class Server:
         """Queue one pair; ``out`` holds pre-allocated output tensors (keys u,
         w, depth, z, valid; u/w/z/valid may be missing).  Returns the ticket."""
         H, W = rig.height, rig.width
-        _dev_f32(I0, (H, W))
-        _dev_f32(I1, (H, W))
-        _dev_f32(out["depth"], (H, W))
+        _need(I0, (H, W), _F32, "I0")
+        _need(I1, (H, W), _F32, "I1")
+        _outputs(out, H, W, "out", required=("depth",))
         tk = ctypes.c_ulonglong()
         _check(lib().vfs_server_submit(self._h, rig.handle, _ptr(I0), _ptr(I1), 4 * W, _ptr(out.get("u")),
                                        _ptr(out.get("w")), _ptr(out["depth"]), _ptr(out.get("z")),

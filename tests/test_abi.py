@@ -114,3 +114,26 @@ def test_server_rejects_bad_configuration(vfs):
     done = ctypes.c_int()
     assert L.vfs_server_poll(None, 1, ctypes.byref(done), None) == -1
     assert L.vfs_server_wait_all(None, 1.0) == -1
+
+
+def test_binding_checks_buffers_before_the_library(vfs):
+    """The binding passes bare pointers, so it checks every tensor's device,
+    dtype and shape, and a batch's per-pair lengths, before calling into the
+    library: mismatches raise here, on the CPU, and nothing is launched."""
+    import types
+
+    import torch
+    rig = types.SimpleNamespace(height=4, width=6, handle=None, levels=1)
+    cpu = torch.zeros((4, 6))
+    with pytest.raises(TypeError, match="CUDA"):
+        vfs.step_rank(cpu, cpu, cpu, cpu)
+    with pytest.raises(ValueError, match="2-D"):
+        vfs.step_gradient(torch.zeros(4), cpu, cpu, cpu)
+    with pytest.raises(ValueError, match="I1s: 0 images for 1 pairs"):
+        vfs.solve_batch(rig, [cpu], [], {})
+    with pytest.raises(ValueError, match="betas: 2 values for 1 pairs"):
+        vfs.solve_batch(rig, [cpu], [cpu], {}, betas=[9.0, 9.0])
+    with pytest.raises(ValueError, match="out: 0 entries for 1 pairs"):
+        vfs.solve_batch_noalloc(rig, [cpu], [cpu], {}, out=[])
+    with pytest.raises(TypeError, match=r"I0s\[0\]: expected a contiguous CUDA tensor"):
+        vfs.solve_probe(rig, [cpu], [cpu], {}, 0, 0)
