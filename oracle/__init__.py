@@ -64,6 +64,10 @@ oracle itself; the tests named live in ``tests/``):
   that breaks brightness constancy (test_oracle_rank).
 * ``triangulate`` -- ground-truth correspondences recover the renderer's
   range; pinhole rectified case gives Z = f b / disparity (test_oracle_geometry).
+* ``upsample`` -- a linear ramp on a full mask returns as twice the ramp at
+  the fine pixel centres; down- then up-sampling a fine ramp returns it
+  doubled; constants inside a random mask return doubled, values outside it
+  never leak, pixels without an in-mask neighbour get 0 (test_oracle_operators).
 """
 from __future__ import annotations
 

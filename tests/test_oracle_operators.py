@@ -239,3 +239,54 @@ def test_energy_is_eq10_written_with_explicit_operators(reg, seed):
     assert np.sum((1.2 * np.hypot(a1, a2))[inside]) > 1e-3 * E
     if reg == "tgv":
         assert np.sum((17.0 * np.sqrt(sum(c * c for c in comps)))[inside]) > 1e-3 * E
+
+
+def test_upsample_closed_forms():
+    """The x2 transfer of (u, w) between pyramid levels (Sec. IV-B; the
+    coarse pixel j covers fine pixels 2j and 2j + 1 of the box pyramid, so
+    its centre sits at fine coordinate 2j + 1/2), pinned by closed forms:
+    (a) a linear ramp on a full mask comes back as twice the ramp sampled at
+    the fine pixel's centre, x = (j_f + 1/2) / 2 - 1/2, wherever both coarse
+    neighbours exist; (b) the box-filtered fine ramp comes back as twice the
+    fine ramp; (c) only coarse pixels inside the mask contribute, with their
+    bilinear weights renormalised: a constant inside the mask comes back as
+    twice the constant wherever any of the four neighbours is inside, values
+    outside the mask never leak, and a fine pixel with no neighbour inside
+    gets 0."""
+    rng = np.random.default_rng(21)
+    Hc, Wc = 7, 9
+    ic, jc = np.mgrid[0:Hc, 0:Wc].astype(np.float64)
+    a, b, c = 0.37, -1.21, 2.5
+    u = a * jc + b * ic + c
+    w = np.stack([-0.8 * jc + 0.3 * ic, 0.45 * jc + 1.7 * ic - 4.0], -1)
+    full = np.ones((Hc, Wc), np.uint8)
+    uf, wf = oracle.upsample(full, u, w)
+    assert uf.shape == (2 * Hc, 2 * Wc) and wf.shape == (2 * Hc, 2 * Wc, 2)
+    i_f, j_f = np.mgrid[0:2 * Hc, 0:2 * Wc].astype(np.float64)
+    x, y = (j_f + 0.5) / 2 - 0.5, (i_f + 0.5) / 2 - 0.5
+    inner = (x >= 0) & (x <= Wc - 1) & (y >= 0) & (y <= Hc - 1)
+    assert np.abs(uf - 2 * (a * x + b * y + c))[inner].max() < 1e-12
+    assert np.abs(wf[..., 0] - 2 * (-0.8 * x + 0.3 * y))[inner].max() < 1e-12
+    assert np.abs(wf[..., 1] - 2 * (0.45 * x + 1.7 * y - 4.0))[inner].max() < 1e-12
+    # (b) down then up: the fine ramp, doubled, away from the clamped border
+    ramp = a * j_f + b * i_f + c
+    back, _ = oracle.upsample(full, oracle.downsample(ramp), np.zeros((Hc, Wc, 2)))
+    assert np.abs(back - 2 * ramp)[1:-1, 1:-1].max() < 1e-12
+    # (c) mask-awareness
+    mask = (rng.random((Hc, Wc)) < 0.6).astype(np.uint8)
+    mask[3, 4] = 0
+    mask[2, 2] = 1
+    uc = np.where(mask == 1, 3.0, 1e6)
+    wc = np.where(mask[..., None] == 1, np.array([-1.5, 0.25]), 1e6)
+    uf, wf = oracle.upsample(mask, uc, wc)
+    for i in range(2 * Hc):
+        for j in range(2 * Wc):
+            x0, y0 = int(np.floor((j + 0.5) / 2 - 0.5)), int(np.floor((i + 0.5) / 2 - 0.5))
+            nb = [(min(max(yy, 0), Hc - 1), min(max(xx, 0), Wc - 1)) for yy in (y0, y0 + 1) for xx in (x0, x0 + 1)]
+            x, y = (j + 0.5) / 2 - 0.5, (i + 0.5) / 2 - 0.5
+            wts = [(1 - abs(x - xx)) * (1 - abs(y - yy)) for yy in (y0, y0 + 1) for xx in (x0, x0 + 1)]
+            inside = any(mask[p] and wt > 0 for p, wt in zip(nb, wts))
+            if inside:
+                assert abs(uf[i, j] - 6.0) < 1e-12 and np.abs(wf[i, j] - [-3.0, 0.5]).max() < 1e-12, (i, j)
+            else:
+                assert uf[i, j] == 0.0 and not wf[i, j].any(), (i, j)
