@@ -64,6 +64,9 @@ oracle itself; the tests named live in ``tests/``):
   that breaks brightness constancy (test_oracle_rank).
 * ``triangulate`` -- ground-truth correspondences recover the renderer's
   range; pinhole rectified case gives Z = f b / disparity (test_oracle_geometry).
+* ``downsample`` -- a linear ramp returns as the ramp at the coarse pixel
+  centres, a +-1 checkerboard vanishes, the total is a quarter of the fine
+  one, an odd last row / column is dropped (test_oracle_operators).
 * ``upsample`` -- a linear ramp on a full mask returns as twice the ramp at
   the fine pixel centres; down- then up-sampling a fine ramp returns it
   doubled; constants inside a random mask return doubled, values outside it

@@ -290,3 +290,22 @@ def test_upsample_closed_forms():
                 assert abs(uf[i, j] - 6.0) < 1e-12 and np.abs(wf[i, j] - [-3.0, 0.5]).max() < 1e-12, (i, j)
             else:
                 assert uf[i, j] == 0.0 and not wf[i, j].any(), (i, j)
+
+
+def test_downsample_closed_forms():
+    """The box pyramid (Sec. IV-B: 2x2 averages, scale 1/2), pinned by closed
+    forms: a linear ramp comes back as the ramp at the coarse pixel's centre
+    (fine coordinate 2j + 1/2), a +-1 checkerboard vanishes, the total is a
+    quarter of the fine one, and an odd last row / column is dropped."""
+    H, W = 9, 12
+    i, j = np.mgrid[0:H, 0:W].astype(np.float64)
+    a, b, c = 0.61, -0.29, 1.75
+    d = oracle.downsample(a * j + b * i + c)
+    assert d.shape == (H // 2, W // 2)
+    ic, jc = np.mgrid[0:H // 2, 0:W // 2].astype(np.float64)
+    assert np.abs(d - (a * (2 * jc + 0.5) + b * (2 * ic + 0.5) + c)).max() < 1e-12
+    checker = np.where((i + j) % 2 == 0, 1.0, -1.0)
+    assert np.abs(oracle.downsample(checker)).max() == 0.0
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=(H, W))
+    assert abs(oracle.downsample(x).sum() * 4 - x[:H - 1, :].sum()) < 1e-10
