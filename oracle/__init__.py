@@ -22,7 +22,9 @@ oracle itself; the tests named live in ``tests/``):
 * ``trajectory_field`` -- tangency to the brute-force epipolar curve traced by
   projecting points at 400 depths along back-projected rays; exact (+1, 0)
   for a pinhole with x-translation; radial field for z-translation;
-  independence of |t| and of the surface depth; analytic Jacobian direction
+  independence of |t| and of the surface depth; analytic Jacobian direction;
+  the epipole flag set is exactly the 2-degree cone around +-t by the
+  equidistant closed form, with zero tangents there and unit ones elsewhere
   (test_oracle_geometry).
 * ``calibration_field`` / ``prerotate`` -- zero field for R = I and equal
   cameras; a scene rendered by a rotated camera and pre-rotated matches the

@@ -287,3 +287,29 @@ def test_triangulation_pinhole_rectified_depth():
     depth, Z, valid = oracle.triangulate(PH, np.eye(3), [b, 0.0, 0.0], w, np.ones(disp.shape, np.uint8))
     assert valid.all()
     assert np.max(np.abs(Z - PH["fx"] * b / disp) / Z) < 1e-9
+
+
+@pytest.mark.parametrize("t", [(0.2, 0.0, 0.0), (0.0, 0.0, -0.15), (0.1, -0.1, 0.05)])
+def test_epipole_guard_is_the_2_degree_cone_around_the_baseline(t):
+    """The trajectory field is undefined at the epipoles (Sec. III-B): the
+    pixels flagged are exactly those whose ray, by the equidistant closed
+    form theta = r / f, lies within 2 degrees of +t or -t (R = I), and those
+    pixels carry a zero tangent; all others carry a unit one.  Pixels within
+    1e-9 of the cone's boundary are not judged."""
+    g, epi = oracle.trajectory_field(EQ, np.eye(3), list(t), 0)
+    H, W = EQ["height"], EQ["width"]
+    i, j = np.mgrid[0:H, 0:W].astype(np.float64)
+    dx, dy = j - EQ["cx"], i - EQ["cy"]
+    th = np.hypot(dx, dy) / EQ["fx"]
+    ph = np.arctan2(dy, dx)
+    ray = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], -1)
+    tu = np.asarray(t, np.float64) / np.linalg.norm(t)
+    ct = np.abs(ray @ tu)
+    lim = np.cos(np.deg2rad(2.0))
+    judged = (np.abs(ct - lim) > 1e-9) & (th < np.deg2rad(EQ["fov_deg"]) / 2)
+    want = ct > lim
+    assert want[judged].any(), "the cone must reach the image for this check"
+    assert np.array_equal(epi.astype(bool)[judged], want[judged])
+    n = np.linalg.norm(g, axis=-1)
+    assert np.all(n[epi.astype(bool)] == 0.0)
+    assert np.allclose(n[judged & ~want], 1.0, atol=1e-12)
