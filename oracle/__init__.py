@@ -26,6 +26,9 @@ oracle itself; the tests named live in ``tests/``):
   the epipole flag set is exactly the 2-degree cone around +-t by the
   equidistant closed form, with zero tangents there and unit ones elsewhere
   (test_oracle_geometry).
+* ``mask0`` -- the pixels whose normalised radius is at most the radial map
+  at half the field of view, by each model's closed form (test_oracle_geometry);
+  ``level_mask`` -- nearest-neighbour sampling at 2^l i + 2^(l-1) (same file).
 * ``calibration_field`` / ``prerotate`` -- zero field for R = I and equal
   cameras; a scene rendered by a rotated camera and pre-rotated matches the
   unrotated render (test_oracle_geometry).

@@ -313,3 +313,27 @@ def test_epipole_guard_is_the_2_degree_cone_around_the_baseline(t):
     n = np.linalg.norm(g, axis=-1)
     assert np.all(n[epi.astype(bool)] == 0.0)
     assert np.allclose(n[judged & ~want], 1.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("cam", [KB, EQ, PH], ids=["kb", "equidistant", "pinhole"])
+def test_image_circle_mask_closed_form(cam):
+    """The level-0 mask (Sec. IV-B) is the set of pixels whose normalised
+    radius is at most the radial map at half the field of view: theta for the
+    equidistant model, tan(theta) for the pinhole, the Kannala-Brandt
+    polynomial theta (1 + k1 theta^2 + ... + k4 theta^8); pixels within 1e-9
+    of the boundary are not judged."""
+    m = oracle.mask0(cam).astype(bool)
+    H, W = cam["height"], cam["width"]
+    i, j = np.mgrid[0:H, 0:W].astype(np.float64)
+    rn = np.hypot((j - cam["cx"]) / cam["fx"], (i - cam["cy"]) / cam["fy"])
+    th = np.deg2rad(cam["fov_deg"]) / 2
+    if cam["model"] == "pinhole":
+        rmax = np.tan(th)
+    else:
+        k1, k2, k3, k4 = cam["k"]
+        rmax = th * (1 + k1 * th ** 2 + k2 * th ** 4 + k3 * th ** 6 + k4 * th ** 8)
+    judged = np.abs(rn - rmax) > 1e-9
+    assert np.array_equal(m[judged], (rn <= rmax)[judged])
+    assert m.any()
+    if cam["model"] != "pinhole":
+        assert not m[0, 0] and not m[-1, -1]     # the image circle leaves the corners out
