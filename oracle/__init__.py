@@ -67,6 +67,9 @@ oracle itself; the tests named live in ``tests/``):
   and room matches the renderer's ground truth (test_oracle_solver).  With
   the rank data term on the plane: unaffected by a tone-curve change of I1
   that breaks brightness constancy (test_oracle_rank).
+* ``clip_accumulate`` -- hand-computed increments above, below, inside and at
+  the edge of the 0.2 px clip; with no clip, one warp's w is u times the
+  tangent (test_oracle_solver).
 * ``triangulate`` -- ground-truth correspondences recover the renderer's
   range; pinhole rectified case gives Z = f b / disparity (test_oracle_geometry).
 * ``downsample`` -- a linear ramp returns as the ramp at the coarse pixel

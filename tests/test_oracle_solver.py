@@ -343,3 +343,17 @@ def test_identical_or_textureless_pairs_give_zero_displacement(reg, c1_inputs):
         o = oracle.solve(rig["cam0"], rig["cam1"], rig["R"], rig["t"], params, A, B)
         assert not o["u"].any() and not o["w"].any()
         assert not o["valid"].any()
+
+
+def test_clip_and_accumulate_worked_values():
+    """Sec. III-C / Algorithm 1: a warp's increment du = u - u_w is clipped to
+    [-0.2, 0.2] px element by element, u becomes u_w + du and w moves by du
+    along the warped tangent.  Hand-computed values: an increment above,
+    below and inside the clip, and exactly at its edge."""
+    u_w = np.array([[1.0, 1.0, 1.0, -2.0]])
+    u = np.array([[1.5, 0.7, 1.1, -1.8]])
+    gw = np.array([[[0.6, 0.8], [1.0, 0.0], [0.0, -1.0], [-0.8, 0.6]]])
+    w = np.array([[[10.0, 20.0], [-3.0, 4.0], [0.5, 0.5], [0.0, 0.0]]])
+    u2, w2 = oracle.clip_accumulate(0.2, u_w, gw, u, w)
+    np.testing.assert_allclose(u2, [[1.2, 0.8, 1.1, -1.8]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w2, [[[10.12, 20.16], [-3.2, 4.0], [0.5, 0.4], [-0.16, 0.12]]], rtol=0, atol=1e-14)
