@@ -49,7 +49,9 @@ oracle itself; the tests named live in ``tests/``):
   (test_oracle_solver).
 * ``linearise`` -- the warped tangent is unit length and radial away from
   the epipole of a radial field, goes to zero approaching it and is
-  Lipschitz across it (test_oracle_solver).
+  Lipschitz across it; on linear images with a constant tangent (where
+  every sample is exact) I_u and rho_c equal their closed forms, and both
+  are 0 where the data term is off (test_oracle_solver).
 * ``rectify_rotations`` / ``rectify`` / ``unrectify`` -- the two virtual
   cameras differ by a pure x-translation for random rigs; rectified renders
   match the renderer's own pinhole renders of the same scene from both

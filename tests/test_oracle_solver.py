@@ -357,3 +357,36 @@ def test_clip_and_accumulate_worked_values():
     u2, w2 = oracle.clip_accumulate(0.2, u_w, gw, u, w)
     np.testing.assert_allclose(u2, [[1.2, 0.8, 1.1, -1.8]], rtol=0, atol=1e-15)
     np.testing.assert_allclose(w2, [[[10.12, 20.16], [-3.2, 4.0], [0.5, 0.4], [-0.16, 0.12]]], rtol=0, atol=1e-14)
+
+
+def test_linearisation_closed_form_on_linear_images():
+    """Eqs. (3), (5) at y = x + w, pinned where every sample is exact:
+    bilinear sampling reproduces a linear image and Keys' bicubic kernel
+    reproduces a constant field, so with I1 = a x + b y + c, I0 = d x + e y
+    + f and the unit tangent (cos p, sin p) everywhere, the one-sided
+    difference along the tangent is I_u = a cos p + b sin p, and
+    rho_c = I1(x + w) - I0(x) - u I_u, at every pixel whose samples stay
+    inside the image; where the data term is off both are 0; u_w = u."""
+    H, W = 24, 30
+    i, j = np.mgrid[0:H, 0:W].astype(np.float64)
+    a, b, c, d, e, f = 0.013, -0.021, 0.4, -0.007, 0.011, 0.3
+    I1 = a * j + b * i + c
+    I0 = d * j + e * i + f
+    p = 0.7
+    gam = np.broadcast_to(np.array([np.cos(p), np.sin(p)]), (H, W, 2)).copy()
+    wv = np.array([1.3, -0.6])
+    w = np.broadcast_to(wv, (H, W, 2)).copy()
+    rng = np.random.default_rng(8)
+    u = rng.uniform(-2, 2, (H, W))
+    dvalid = (rng.random((H, W)) < 0.8).astype(np.uint8)
+    uw, gw, Iu, rho = oracle.linearise(I0, I1, gam, dvalid, u, w)
+    inner = np.zeros((H, W), bool)
+    inner[3:-3, 3:-3] = True
+    on = inner & (dvalid == 1)
+    Iu_want = a * np.cos(p) + b * np.sin(p)
+    rho_want = (a * (j + wv[0]) + b * (i + wv[1]) + c) - I0 - u * Iu_want
+    assert np.abs(gw - gam)[inner].max() < 1e-12
+    assert np.abs(Iu - Iu_want)[on].max() < 1e-12
+    assert np.abs(rho - rho_want)[on].max() < 1e-12
+    assert not Iu[dvalid == 0].any() and not rho[dvalid == 0].any()
+    assert np.array_equal(uw, u)
