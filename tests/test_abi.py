@@ -68,6 +68,9 @@ def test_rig_create_rejects_bad_arguments(vfs):
     assert _create(vfs, cam0=dict(CAM, fx=0.0))[0] == -1
     st, msg = _create(vfs, t=(0.0, 0.0, 0.0))
     assert "baseline" in msg
+    wide = dict(CAM, width=(1 << 20) + 32, cx=float(1 << 19))                       # above the row limit
+    st, msg = _create(vfs, cam0=wide, cam1=wide)
+    assert st == -1 and "width above" in msg
     L = vfs.lib()
     assert L.vfs_rig_create(None, None, None, None, 3, None, None) == -1
 
@@ -90,6 +93,11 @@ def test_solve_and_steps_reject_bad_arguments(vfs):
                              3, None) == -1
         assert "pass_iters" in L.vfs_last_error().decode()
     assert L.vfs_step_upsample(4, 4, 2, one, one, one, 8, one, one, None) == -1
+    big = (1 << 20) + 1                                                               # rows above 2^20 elements
+    assert L.vfs_step_pd(big, 1, big, one, one, one, one, one, one, one, one, one, one, one, ctypes.byref(p), 3,
+                         None) == -1
+    assert L.vfs_step_pd(0, 1, 1, one, one, one, one, one, one, one, one, one, one, one, ctypes.byref(p), 3,
+                         None) == -1                                                  # empty image
     assert L.vfs_profile_enable(None, 1) == -1
 
 
