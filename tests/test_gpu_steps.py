@@ -420,3 +420,42 @@ def test_triangulate(vfs, cid):
     assert np.all(rel <= bar), (rel.max(), (rel / bar).max())
     assert np.all(np.abs(_np(z)[ok] - zo[ok]) / do[ok] <= bar)
     assert np.all(np.isinf(_np(depth)[~vg]))
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (5, 3), (2, 70), (63, 2), (57, 9)])
+@pytest.mark.parametrize("npass", [2, 3, 4])
+def test_primal_dual_degenerate_sizes(vfs, W, H, npass):
+    """K = 9 iterations of Eq. (11) on images smaller than one wavefront's
+    strip or one march's halo (a single pixel, a few rows or columns, one
+    strip with its halo lanes past the image): every pass kernel against the
+    FP64 oracle at the step bar, with the first pass of a warp and a
+    remainder launch (9 = N + a multiple of N + a remainder for N = 2, 4)."""
+    import torch
+    K = 9
+    rng = np.random.default_rng(100 * W + H)
+    m = (rng.random((H, W)) < 0.85).astype(np.uint8)
+    m[0, 0] = 1
+    mx = np.zeros_like(m)
+    mx[:, :-1] = m[:, :-1] & m[:, 1:]
+    my = np.zeros_like(m)
+    my[:-1] = m[:-1] & m[1:]
+    data = m & (rng.random((H, W)) < 0.9).astype(np.uint8)
+    flags = (m | (mx << 1) | (my << 2) | (data << 3)).astype(np.uint8)
+    J0 = rng.uniform(0.1, 0.9, (H, W)).astype(np.float32)
+    T = oracle.tensor(f32(J0), m, 9.0, 0.85).astype(np.float32)
+    Iu = (rng.normal(0, 0.05, (H, W)) * data).astype(np.float32)
+    rho = (rng.normal(0, 0.05, (H, W)) * data).astype(np.float32)
+    u = (1.5 + 0.3 * rng.random((H, W))).astype(np.float32)
+    v = (0.05 * rng.normal(size=(H, W, 2)) * m[..., None]).astype(np.float32)
+    p = (oracle.project_balls(0.7 * rng.normal(size=(H, W, 2)), 2).reshape(H, W, 2) * m[..., None]).astype(np.float32)
+    q = (oracle.project_balls(0.7 * rng.normal(size=(H, W, 4)), 4).reshape(H, W, 4) * m[..., None]).astype(np.float32)
+    params = dict(configs.PAPER_PARAMS, levels=1, warps=1, iters=K, reg="tgv", pass_iters=npass)
+    tpack = np.concatenate([T, Iu[..., None]], -1).astype(np.float32)
+    tu, tv, tp, tq = _t(u), _t(v), _t(p), _t(q)
+    print("degenerate", W, H, npass, flush=True)
+    vfs.step_pd(_t(tpack), _t(rho), _t(flags), tu, tv, tp, tq, params, K)
+    torch.cuda.synchronize()
+    sp, su, sv = oracle.steps(f32(T), m, params["alpha0"], params["alpha1"], "tgv")
+    st = oracle.pd_iterations(params, f32(T), m, sp, su, sv, f32(Iu), f32(rho), f32(u), f32(v), f32(p), f32(q), K)
+    for k, g in (("u", tu), ("v", tv), ("p", tp), ("q", tq)):
+        assert np.max(np.abs(_np(g) - st[k])) < 2e-5, k
