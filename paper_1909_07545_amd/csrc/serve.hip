@@ -350,7 +350,14 @@ void finish_request(vfs_server* sv, Request* r, int state)
 {
     r->t_done = Clock::now();
     r->state.store(state);
-    sv->outstanding.fetch_sub(1);
+    {
+        // under the lock: a vfs_server_wait_all that has just seen requests
+        // outstanding is then already waiting when the notification comes
+        // (a decrement between its check and its wait would otherwise leave
+        // it asleep until its time-out)
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->outstanding.fetch_sub(1);
+    }
     sv->cv.notify_all();
 }
 
