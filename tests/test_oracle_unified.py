@@ -16,7 +16,7 @@ import torch
 
 import oracle
 from synth import configs, scene
-from tests.test_oracle_geometry import _angle, _brute_force_tangent, _pixels, _rot
+from tests.test_oracle_geometry import _angle, _brute_force_tangent, _pixels
 
 BASE = dict(width=320, height=240, fx=90.0, fy=90.0, cx=159.5, cy=119.5, fov_deg=180.0)
 UCMS = [dict(BASE, model="unified", k=(xi, 0.0, 0.0, 0.0)) for xi in (0.4, 1.0, 1.6)]
