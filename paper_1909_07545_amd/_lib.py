@@ -268,8 +268,9 @@ def solve_batch(rig: Rig, I0s, I1s, params: dict, betas=None, etas=None, stream=
     n = _batch_args(rig, I0s, I1s, betas, etas, out)
     H, W = rig.height, rig.width
     if out is None:
-        out = [dict(u=torch.empty((H, W), device="cuda"), w=torch.empty((H, W, 2), device="cuda"),
-                    depth=torch.empty((H, W), device="cuda"), z=torch.empty((H, W), device="cuda"),
+        f32 = dict(dtype=torch.float32, device="cuda")     # whatever torch's default dtype is
+        out = [dict(u=torch.empty((H, W), **f32), w=torch.empty((H, W, 2), **f32),
+                    depth=torch.empty((H, W), **f32), z=torch.empty((H, W), **f32),
                     valid=torch.empty((H, W), dtype=torch.uint8, device="cuda")) for _ in range(n)]
     arr = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])  # noqa: E731
     p = _params(params)
